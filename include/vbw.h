@@ -1,0 +1,178 @@
+/*
+ * vbw.h -- C ABI of the MI355X (gfx950) overlap-save variable-bandwidth filter.
+ *
+ * Operation (Moryakova & Johansson, arXiv 2406.14116):
+ *   Sec. II, overlap-save steps 1-5: every channel is cut into N-sample
+ *   segments that advance by M samples (`hop`); each segment is transformed by
+ *   an N-point DFT, multiplied by the filter DFT coefficients H(k), inverse
+ *   transformed (eq. (4): +j exponent, factor 1/N), the first N-M samples are
+ *   dropped and the M-sample pieces are concatenated.
+ *   Sec. III-B, eqs. (5)-(7): H(k) = H_R(k) exp(-j 2 pi k D / N) with
+ *   D = (L-1)/2 = (N-M)/2, and H_R(k) = 1 on the passband bins
+ *   [0,k1-1] u [N-k1+1,N-1], V(k-k1) on the transition bins [k1,k2], V(N-k-k1)
+ *   on the mirrored transition bins [N-k2,N-k1], and 0 on the stopband bins,
+ *   with k2 = k1 + L_V - 1.  The L_V values V(r) are shared by every bandwidth,
+ *   so a bandwidth change is an integer k1 and costs no arithmetic
+ *   (Sec. III-D, last paragraph).
+ *
+ * Framing: segment m covers input samples [m*M - (N-M), m*M + M); samples
+ * outside [0, len) read as zero (N-M zeros of history before the stream).
+ * Output sample m*M + j (j < M) is sample N-M+j of block m's inverse
+ * transform; output length equals input length.  Block count per channel is
+ * ceil(len / M).
+ *
+ * Data layout: each channel's input and output is one contiguous device
+ * array of `len` complex samples, interleaved (re, im):
+ *   VBW_C64   -- two float32 per sample (8 bytes)
+ *   VBW_CF16  -- two IEEE binary16 per sample (4 bytes)
+ *   VBW_CBF16 -- two bfloat16 per sample (4 bytes)
+ * Arithmetic is float32 in every case; 16-bit values are converted on load
+ * and rounded to nearest-even on store.  With VBW_F32_OUT the output is
+ * written as float32 pairs whatever the input storage.
+ *
+ * Errors: every entry point returns a vbw_status; negative values are errors.
+ * No exception crosses the ABI and nothing aborts.  A call that fails leaves
+ * the plan as it was.  Device failures map to VBW_EDEVICE, allocation
+ * failures to VBW_ENOMEM.
+ *
+ * Threading: one plan is used by one host thread at a time; distinct plans are
+ * independent.  All vbw_filter calls on one plan must be ordered (same stream,
+ * or the caller synchronizes between streams): the plan's device tables are
+ * updated stream-ordered by the next vbw_filter call.
+ */
+#ifndef VBW_H
+#define VBW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum vbw_status {
+    VBW_OK = 0,
+    VBW_EINVAL = -1,        /* malformed argument (see each call) */
+    VBW_ERANGE = -2,        /* k1 / L_V outside the admissible bin range */
+    VBW_ENOMEM = -3,        /* host or device allocation failed */
+    VBW_EDEVICE = -4,       /* HIP runtime or kernel launch error */
+    VBW_EUNSUPPORTED = -5   /* valid request this build does not serve */
+} vbw_status;
+
+typedef enum vbw_dtype {
+    VBW_C64 = 0,
+    VBW_CF16 = 1,
+    VBW_CBF16 = 2
+} vbw_dtype;
+
+typedef enum vbw_engine {
+    VBW_ENGINE_FFT = 0,     /* LDS-staged Stockham FFT, float32 */
+    VBW_ENGINE_GEMM = 1     /* small DFTs as MFMA GEMMs (16-bit storage only) */
+} vbw_engine;
+
+/* Plan flags. */
+#define VBW_NO_PRUNE   (1u << 0)  /* always run the full N-point inverse */
+#define VBW_GRAPH      (1u << 1)  /* replay a captured HIP graph in steady state */
+#define VBW_F32_OUT    (1u << 2)  /* write float32 output for 16-bit input */
+#define VBW_HOST_ONLY  (1u << 3)  /* validate and build host tables only; no device use */
+#define VBW_AUTOTUNE   (1u << 4)  /* time the launch variants once at plan time */
+
+/* One channel.  `reserved` must be 0. */
+typedef struct vbw_channel {
+    int32_t n;          /* DFT size N: a power of two, 16 <= N <= 4096 */
+    int32_t hop;        /* output samples per block M: 1 <= M <= N-1, N-M even */
+    int32_t lv;         /* transition samples per edge L_V >= 0 */
+    int32_t v_offset;   /* index of V(0) in the plan's V pool */
+    int32_t k1;         /* first transition bin in force from block 0 */
+    int32_t reserved;
+    int64_t len;        /* input and output length in complex samples, >= 0 */
+} vbw_channel;
+
+/* Plan description.  The library deep-copies `channels` and `v_pool`; the
+ * caller may free them when vbw_plan returns.  V values are rounded to
+ * float32 once, here.  `reserved` must be 0. */
+typedef struct vbw_plan_desc {
+    int32_t n_channels;            /* >= 1 */
+    int32_t n_v;                   /* entries in v_pool, >= 0 */
+    const vbw_channel *channels;   /* host array of n_channels */
+    const double *v_pool;          /* host array of n_v finite values */
+    int32_t dtype;                 /* vbw_dtype */
+    int32_t engine;                /* vbw_engine */
+    uint32_t flags;                /* VBW_* flags */
+    int32_t reserved;
+} vbw_plan_desc;
+
+typedef struct vbw_plan_s *vbw_plan_t;
+
+/* Create a plan (Sec. II framing, Sec. III-B coefficients).
+ * Validates every channel, copies descriptors and V, builds the integer work
+ * list and uploads the device tables (float32 twiddles generated in float64
+ * and rounded to nearest).  Uses the current HIP device.
+ * Errors: VBW_EINVAL for a NULL pointer, a bad N / hop / L_V / v_offset /
+ * len, a non-finite V, an unknown dtype/engine/flag or nonzero reserved
+ * field; VBW_ERANGE when k1 < 1 or k2 = k1 + L_V - 1 > N/2 - 1 (the one
+ * exception is the all-pass L_V = 0, k1 = N/2 + 1); VBW_EUNSUPPORTED for the
+ * GEMM engine with float32 storage; VBW_ENOMEM / VBW_EDEVICE from HIP.
+ * On error *out is set to NULL. */
+vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out);
+
+/* Change channel `channel`'s bandwidth from block `from_block` on
+ * (Sec. III-B: only the integer edge k1 changes; V is reused, nothing is
+ * recomputed).  Block m uses the entry with the largest from_block <= m; an
+ * entry with an equal from_block is replaced.  O(entries) host work, no device
+ * call; the change reaches the device with the next vbw_filter.
+ * Errors: VBW_EINVAL (NULL plan, channel out of range, from_block < 0,
+ * more than 4096 entries on one channel); VBW_ERANGE (k1 as in vbw_plan). */
+vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
+                             int64_t from_block);
+
+/* Filter every channel (Sec. II steps 1-5) from zero history.
+ * x[c] / y[c] are device pointers to channel c's input / output
+ * (layout above); the host arrays x and y hold n_channels pointers and are
+ * read during the call only.  The device buffers are caller-owned and must
+ * stay valid until the work on `stream` completes.  `stream` is a
+ * hipStream_t (NULL: the null stream).  Asynchronous: no host
+ * synchronisation except when pointer or schedule tables must be re-uploaded
+ * while an earlier upload is still in flight.
+ * Errors: VBW_EINVAL (NULL plan or arrays, NULL pointer for a channel with
+ * len > 0, an output range overlapping any other input or output range);
+ * VBW_EUNSUPPORTED for a VBW_HOST_ONLY plan; VBW_EDEVICE from HIP. */
+vbw_status vbw_filter(vbw_plan_t plan, const void *const *x, void *const *y,
+                      void *stream);
+
+/* Release the plan and its device tables (NULL is a no-op).  Synchronizes
+ * with work the plan has queued. */
+void vbw_destroy(vbw_plan_t plan);
+
+/* Static description of a status code. */
+const char *vbw_strerror(vbw_status status);
+
+/* Host-side introspection, for tests and tooling. */
+typedef enum vbw_query {
+    VBW_Q_N_CHANNELS = 0,
+    VBW_Q_N_ITEMS = 1,         /* work items in the launch */
+    VBW_Q_TOTAL_BLOCKS = 2,    /* sum over channels of ceil(len/M) */
+    VBW_Q_TOTAL_SAMPLES = 3,   /* sum over channels of len */
+    VBW_Q_WORKGROUP = 4,       /* threads per workgroup */
+    VBW_Q_LDS_BYTES = 5,       /* LDS per workgroup */
+    VBW_Q_GRID = 6,            /* workgroups per launch */
+    VBW_Q_KERNEL_VARIANT = 7   /* index of the chosen launch variant */
+} vbw_query;
+
+/* Value of `q` for the plan, or a negative vbw_status. */
+int64_t vbw_plan_query(vbw_plan_t plan, int32_t q);
+
+/* k1 in force for (channel, block) after every vbw_set_bandwidth so far, or a
+ * negative vbw_status. */
+int32_t vbw_block_k1(vbw_plan_t plan, int32_t channel, int64_t block);
+
+/* The float32 twiddle table the plan uploads for size n (a power of two,
+ * 2 <= n <= 4096): out[2r] = RN(cos(2 pi r/n)), out[2r+1] = RN(-sin(2 pi r/n)),
+ * r < n, generated in float64 and rounded to nearest float32 (eq. (4) sign
+ * convention: exp(-j 2 pi r / n)). */
+vbw_status vbw_twiddle_table(int32_t n, float *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VBW_H */

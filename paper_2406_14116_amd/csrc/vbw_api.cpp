@@ -1,0 +1,561 @@
+// vbw_api.cpp -- plan object, validation, integer planner, device tables and
+// the C ABI declared in include/vbw.h.
+//
+// Paper: Moryakova & Johansson, arXiv 2406.14116.  The plan implements the
+// problem statement of Sec. III-A/B: a fixed transition width, a variable
+// band edge discretised to bins (eq. (7)), and one stored set of L_V
+// transition values V(r) so that a bandwidth change is an integer update with
+// no arithmetic (Sec. III-D).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "vbw.h"
+#include "vbw_internal.h"
+
+using vbw::ChannelDev;
+using vbw::SchedDev;
+using vbw::WorkItem;
+
+namespace {
+
+constexpr int kMaxSchedPerChannel = 4096;
+constexpr uint32_t kKnownFlags = VBW_NO_PRUNE | VBW_GRAPH | VBW_F32_OUT | VBW_HOST_ONLY | VBW_AUTOTUNE;
+
+vbw_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return VBW_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return VBW_ENOMEM;
+    return VBW_EDEVICE;
+}
+
+// Test hook: VBW_FAIL_DEVICE_ALLOC=k makes the k-th device allocation made by
+// one vbw_plan call fail (1-based), to exercise the ENOMEM path without leaks.
+thread_local int g_alloc_count = 0;
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    ++g_alloc_count;
+    if (const char *s = std::getenv("VBW_FAIL_DEVICE_ALLOC")) {
+        if (std::atoi(s) == g_alloc_count) return hipErrorOutOfMemory;
+    }
+    if (bytes == 0) bytes = 16;
+    return hipMalloc(p, bytes);
+}
+
+bool is_pow2(int32_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int ilog2(int32_t n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+int64_t n_blocks_of(int64_t len, int32_t hop) { return len <= 0 ? 0 : (len + hop - 1) / hop; }
+
+// Admissible edge for channel shape (n, lv): k1 >= 1 and k2 = k1 + lv - 1 <=
+// N/2 - 1 (the Nyquist bin is stopband), or the all-pass lv = 0, k1 = N/2+1.
+bool k1_in_range(int32_t n, int32_t lv, int32_t k1) {
+    if (lv == 0 && k1 == n / 2 + 1) return true;
+    return k1 >= 1 && int64_t(k1) + lv - 1 <= n / 2 - 1;
+}
+
+// cos(2 pi r / n), sin(2 pi r / n) in float64 with exact octant reduction
+// (r / n is a dyadic rational, so every reflection below is exact).
+void cos_sin_2pi(int64_t r, int64_t n, double *c, double *s) {
+    r %= n;
+    if (r < 0) r += n;
+    // y = r / n in [0, 1)
+    double sign_s = 1.0, sign_c = 1.0;
+    int64_t num = r, den = n;
+    if (2 * num > den) {            // y in (1/2, 1): sin(2 pi y) = -sin(2 pi (1 - y))
+        num = den - num;
+        sign_s = -1.0;
+    }
+    if (4 * num > den) {            // y in (1/4, 1/2]: cos = -cos(2 pi (1/2 - y)), sin same
+        num = den - 2 * num;        // (1/2 - y) = (den - 2 num) / (2 den)
+        den = 2 * den;
+        sign_c = -1.0;
+    }
+    bool swap = false;
+    if (8 * num > den) {            // y in (1/8, 1/4]: cos(2 pi y) = sin(2 pi (1/4 - y))
+        num = den - 4 * num;        // (1/4 - y) = (den - 4 num) / (4 den)
+        den = 4 * den;
+        swap = true;
+    }
+    const double a = 6.283185307179586476925286766559 * (double(num) / double(den));
+    double cc = std::cos(a), ss = std::sin(a);
+    if (swap) std::swap(cc, ss);
+    *c = sign_c * cc;
+    *s = sign_s * ss;
+}
+
+struct Sched {
+    std::vector<std::pair<int64_t, int32_t>> e;  // (from_block, k1), sorted, e[0].first == 0
+};
+
+}  // namespace
+
+struct vbw_plan_s {
+    std::vector<vbw_channel> ch;
+    std::vector<float> v32;
+    std::vector<Sched> sched;
+    std::vector<WorkItem> items;
+    int32_t dtype = VBW_C64;
+    int32_t engine = VBW_ENGINE_FFT;
+    uint32_t flags = 0;
+    int log2n_fixed = 0;
+    int64_t total_blocks = 0;
+    int64_t total_samples = 0;
+    int variant = 0;
+
+    // device state
+    bool host_only = true;
+    int device = 0;
+    WorkItem *d_items = nullptr;
+    float *d_v = nullptr;
+    float2 *d_tw = nullptr;
+    unsigned char *d_dyn = nullptr;   // ChannelDev[nch] | x[nch] | y[nch] | SchedDev[cap]
+    size_t dyn_cap_sched = 0;
+    unsigned char *h_stage = nullptr; // pinned staging for d_dyn
+    size_t stage_bytes = 0;
+    hipEvent_t upload_evt = nullptr;
+    hipEvent_t done_evt = nullptr;
+    bool upload_pending = false;
+    bool dyn_valid = false;
+    bool sched_dirty = true;
+    std::vector<const void *> last_x;
+    std::vector<void *> last_y;
+
+    // graph replay
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    size_t dyn_bytes(size_t sched_cap) const {
+        return ch.size() * (sizeof(ChannelDev) + 2 * sizeof(void *)) + sched_cap * sizeof(SchedDev);
+    }
+    size_t sched_entries() const {
+        size_t s = 0;
+        for (auto &c : sched) s += c.e.size();
+        return s;
+    }
+};
+
+namespace {
+
+vbw_status validate_desc(const vbw_plan_desc *d) {
+    if (!d || !d->channels || d->n_channels < 1 || d->n_v < 0 || (d->n_v > 0 && !d->v_pool))
+        return VBW_EINVAL;
+    if (d->reserved != 0 || (d->flags & ~kKnownFlags) != 0) return VBW_EINVAL;
+    if (d->dtype != VBW_C64 && d->dtype != VBW_CF16 && d->dtype != VBW_CBF16) return VBW_EINVAL;
+    if (d->engine != VBW_ENGINE_FFT && d->engine != VBW_ENGINE_GEMM) return VBW_EINVAL;
+    for (int32_t i = 0; i < d->n_v; ++i)
+        if (!std::isfinite(d->v_pool[i])) return VBW_EINVAL;
+    vbw_status range = VBW_OK;
+    for (int32_t c = 0; c < d->n_channels; ++c) {
+        const vbw_channel &ch = d->channels[c];
+        if (ch.reserved != 0) return VBW_EINVAL;
+        if (!is_pow2(ch.n) || ch.n < (1 << vbw::kMinLog2N) || ch.n > (1 << vbw::kMaxLog2N)) return VBW_EINVAL;
+        if (ch.hop < 1 || ch.hop > ch.n - 1 || ((ch.n - ch.hop) & 1)) return VBW_EINVAL;
+        if (ch.lv < 0 || ch.lv > ch.n / 2) return VBW_EINVAL;
+        if (ch.v_offset < 0 || int64_t(ch.v_offset) + ch.lv > d->n_v) return VBW_EINVAL;
+        if (ch.len < 0 || n_blocks_of(ch.len, ch.hop) > int64_t(INT32_MAX) - 4096) return VBW_EINVAL;
+        if (!k1_in_range(ch.n, ch.lv, ch.k1)) range = VBW_ERANGE;
+    }
+    if (range != VBW_OK) return range;
+    if (d->engine == VBW_ENGINE_GEMM) return VBW_EUNSUPPORTED;
+    return VBW_OK;
+}
+
+// Work list: each item is up to 4096/N consecutive blocks of one channel,
+// i.e. one 4096-value tile per workgroup.
+void build_items(vbw_plan_s *p) {
+    p->items.clear();
+    p->total_blocks = 0;
+    p->total_samples = 0;
+    int first_log2 = -1;
+    bool uniform = true;
+    for (size_t c = 0; c < p->ch.size(); ++c) {
+        const vbw_channel &ch = p->ch[c];
+        const int64_t nb = n_blocks_of(ch.len, ch.hop);
+        const int lg = ilog2(ch.n);
+        const int per = vbw::kTilePoints / ch.n;
+        p->total_blocks += nb;
+        p->total_samples += ch.len;
+        for (int64_t b = 0; b < nb; b += per) {
+            WorkItem it;
+            it.channel = int32_t(c);
+            it.first_block = int32_t(b);
+            it.n_blocks = int32_t(std::min<int64_t>(per, nb - b));
+            it.log2n = lg;
+            p->items.push_back(it);
+        }
+        if (nb > 0) {
+            if (first_log2 < 0) first_log2 = lg;
+            else if (first_log2 != lg) uniform = false;
+        }
+    }
+    p->log2n_fixed = (uniform && first_log2 > 0) ? first_log2 : 0;
+}
+
+void free_device(vbw_plan_s *p) {
+    if (p->host_only) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    if (p->done_evt) (void)hipEventSynchronize(p->done_evt);
+    if (p->upload_evt) (void)hipEventSynchronize(p->upload_evt);
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_v) (void)hipFree(p->d_v);
+    if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->d_dyn) (void)hipFree(p->d_dyn);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->upload_evt) (void)hipEventDestroy(p->upload_evt);
+    if (p->done_evt) (void)hipEventDestroy(p->done_evt);
+    (void)hipSetDevice(prev);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    p->cap_stream = nullptr;
+    p->d_items = nullptr;
+    p->d_v = nullptr;
+    p->d_tw = nullptr;
+    p->d_dyn = nullptr;
+    p->h_stage = nullptr;
+    p->upload_evt = p->done_evt = nullptr;
+}
+
+void fill_twiddles(int32_t n, float *out) {
+    for (int32_t r = 0; r < n; ++r) {
+        double c, s;
+        cos_sin_2pi(r, n, &c, &s);
+        out[2 * r] = float(c);
+        out[2 * r + 1] = float(-s);
+    }
+}
+
+vbw_status alloc_dyn(vbw_plan_s *p, size_t sched_cap) {
+    void *d = nullptr, *h = nullptr;
+    const size_t bytes = p->dyn_bytes(sched_cap);
+    hipError_t e = dev_alloc(&d, bytes);
+    if (e != hipSuccess) return from_hip(e);
+    e = hipHostMalloc(&h, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return from_hip(e);
+    }
+    if (p->d_dyn) (void)hipFree(p->d_dyn);        // hipFree waits for queued work
+    if (p->h_stage) {
+        if (p->upload_pending) (void)hipEventSynchronize(p->upload_evt);
+        (void)hipHostFree(p->h_stage);
+    }
+    p->d_dyn = static_cast<unsigned char *>(d);
+    p->h_stage = static_cast<unsigned char *>(h);
+    p->stage_bytes = bytes;
+    p->dyn_cap_sched = sched_cap;
+    p->upload_pending = false;
+    p->dyn_valid = false;
+    // the captured graph holds the old table addresses
+    if (p->graph_exec) {
+        (void)hipGraphExecDestroy(p->graph_exec);
+        p->graph_exec = nullptr;
+    }
+    if (p->graph) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    return VBW_OK;
+}
+
+vbw_status setup_device(vbw_plan_s *p) {
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) return from_hip(e);
+    p->host_only = false;
+    void *d = nullptr;
+    if ((e = dev_alloc(&d, p->items.size() * sizeof(WorkItem))) != hipSuccess) return from_hip(e);
+    p->d_items = static_cast<WorkItem *>(d);
+    if ((e = dev_alloc(&d, std::max<size_t>(1, p->v32.size()) * sizeof(float))) != hipSuccess) return from_hip(e);
+    p->d_v = static_cast<float *>(d);
+    if ((e = dev_alloc(&d, vbw::kTwiddleN * sizeof(float2))) != hipSuccess) return from_hip(e);
+    p->d_tw = static_cast<float2 *>(d);
+    if ((e = hipEventCreateWithFlags(&p->upload_evt, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
+    if ((e = hipEventCreateWithFlags(&p->done_evt, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
+    vbw_status st = alloc_dyn(p, std::max<size_t>(p->sched_entries(), 2 * p->ch.size()));
+    if (st != VBW_OK) return st;
+
+    std::vector<float> tw(2 * vbw::kTwiddleN);
+    fill_twiddles(vbw::kTwiddleN, tw.data());
+    if (!p->items.empty() &&
+        (e = hipMemcpy(p->d_items, p->items.data(), p->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice)) != hipSuccess)
+        return from_hip(e);
+    if (!p->v32.empty() &&
+        (e = hipMemcpy(p->d_v, p->v32.data(), p->v32.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return from_hip(e);
+    if ((e = hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return from_hip(e);
+    if (p->flags & VBW_GRAPH) {
+        if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) return from_hip(e);
+    }
+    return VBW_OK;
+}
+
+size_t elem_bytes_in(const vbw_plan_s *p) { return p->dtype == VBW_C64 ? 8 : 4; }
+size_t elem_bytes_out(const vbw_plan_s *p) {
+    return (p->dtype == VBW_C64 || (p->flags & VBW_F32_OUT)) ? 8 : 4;
+}
+
+// Every output range must be disjoint from every other input and output range.
+bool ranges_ok(const vbw_plan_s *p, const void *const *x, void *const *y) {
+    struct R {
+        uintptr_t lo, hi;
+        bool out;
+    };
+    std::vector<R> rs;
+    rs.reserve(2 * p->ch.size());
+    for (size_t c = 0; c < p->ch.size(); ++c) {
+        const int64_t len = p->ch[c].len;
+        if (len == 0) continue;
+        if (!x[c] || !y[c]) return false;
+        const uintptr_t xi = reinterpret_cast<uintptr_t>(x[c]);
+        const uintptr_t yo = reinterpret_cast<uintptr_t>(y[c]);
+        rs.push_back({xi, xi + uintptr_t(len) * elem_bytes_in(p), false});
+        rs.push_back({yo, yo + uintptr_t(len) * elem_bytes_out(p), true});
+    }
+    std::sort(rs.begin(), rs.end(), [](const R &a, const R &b) { return a.lo < b.lo; });
+    // sweep: track the furthest end among intervals seen so far, and whether
+    // the interval reaching it (or any still open) is an output
+    uintptr_t open_hi_in = 0, open_hi_out = 0;
+    for (const R &r : rs) {
+        const bool hits_out = r.lo < open_hi_out;
+        const bool hits_in = r.lo < open_hi_in;
+        if (hits_out || (r.out && hits_in)) return false;
+        if (r.out) open_hi_out = std::max(open_hi_out, r.hi);
+        else open_hi_in = std::max(open_hi_in, r.hi);
+    }
+    return true;
+}
+
+vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipStream_t s) {
+    const size_t nch = p->ch.size();
+    const size_t need = p->sched_entries();
+    if (need > p->dyn_cap_sched) {
+        vbw_status st = alloc_dyn(p, std::max(need, 2 * p->dyn_cap_sched));
+        if (st != VBW_OK) return st;
+    }
+    if (p->upload_pending) {
+        hipError_t e = hipEventSynchronize(p->upload_evt);
+        if (e != hipSuccess) return from_hip(e);
+        p->upload_pending = false;
+    }
+    unsigned char *h = p->h_stage;
+    ChannelDev *hc = reinterpret_cast<ChannelDev *>(h);
+    const void **hx = reinterpret_cast<const void **>(h + nch * sizeof(ChannelDev));
+    void **hy = reinterpret_cast<void **>(h + nch * (sizeof(ChannelDev) + sizeof(void *)));
+    SchedDev *hs = reinterpret_cast<SchedDev *>(h + nch * (sizeof(ChannelDev) + 2 * sizeof(void *)));
+    int32_t so = 0;
+    for (size_t c = 0; c < nch; ++c) {
+        const vbw_channel &ch = p->ch[c];
+        hc[c].len = ch.len;
+        hc[c].n = ch.n;
+        hc[c].hop = ch.hop;
+        hc[c].lv = ch.lv;
+        hc[c].v_offset = ch.v_offset;
+        hc[c].sched_begin = so;
+        hc[c].sched_count = int32_t(p->sched[c].e.size());
+        for (auto &pr : p->sched[c].e) {
+            hs[so].from_block = pr.first;
+            hs[so].k1 = pr.second;
+            hs[so].pad = 0;
+            ++so;
+        }
+        hx[c] = x[c];
+        hy[c] = y[c];
+    }
+    const size_t bytes = p->dyn_bytes(size_t(so));
+    hipError_t e = hipMemcpyAsync(p->d_dyn, h, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return from_hip(e);
+    if ((e = hipEventRecord(p->upload_evt, s)) != hipSuccess) return from_hip(e);
+    p->upload_pending = true;
+    p->dyn_valid = true;
+    p->sched_dirty = false;
+    p->last_x.assign(x, x + nch);
+    p->last_y.assign(y, y + nch);
+    return VBW_OK;
+}
+
+vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
+    const size_t nch = p->ch.size();
+    vbw::LaunchArgs a;
+    a.items = p->d_items;
+    a.ch = reinterpret_cast<const ChannelDev *>(p->d_dyn);
+    a.x = reinterpret_cast<const void *const *>(p->d_dyn + nch * sizeof(ChannelDev));
+    a.y = reinterpret_cast<void *const *>(p->d_dyn + nch * (sizeof(ChannelDev) + sizeof(void *)));
+    a.sched = reinterpret_cast<const SchedDev *>(p->d_dyn + nch * (sizeof(ChannelDev) + 2 * sizeof(void *)));
+    a.v = p->d_v;
+    a.tw = p->d_tw;
+    a.n_items = int32_t(p->items.size());
+    a.xcd_remap = 1;
+    return a;
+}
+
+vbw::Storage storage_of(int32_t dtype) {
+    return dtype == VBW_CF16 ? vbw::Storage::F16 : dtype == VBW_CBF16 ? vbw::Storage::BF16 : vbw::Storage::C64;
+}
+
+hipError_t launch(const vbw_plan_s *p, hipStream_t s) {
+    return vbw::launch_ols_fft(launch_args(p), p->log2n_fixed, storage_of(p->dtype),
+                               (p->flags & VBW_F32_OUT) != 0, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out) {
+    if (!out) return VBW_EINVAL;
+    *out = nullptr;
+    vbw_status st = validate_desc(desc);
+    if (st != VBW_OK) return st;
+    vbw_plan_s *p = new (std::nothrow) vbw_plan_s();
+    if (!p) return VBW_ENOMEM;
+    try {
+        p->ch.assign(desc->channels, desc->channels + desc->n_channels);
+        p->v32.resize(size_t(desc->n_v));
+        for (int32_t i = 0; i < desc->n_v; ++i) p->v32[i] = float(desc->v_pool[i]);
+        p->dtype = desc->dtype;
+        p->engine = desc->engine;
+        p->flags = desc->flags;
+        p->sched.resize(p->ch.size());
+        for (size_t c = 0; c < p->ch.size(); ++c) p->sched[c].e.push_back({0, p->ch[c].k1});
+        build_items(p);
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return VBW_ENOMEM;
+    }
+    if (!(desc->flags & VBW_HOST_ONLY)) {
+        g_alloc_count = 0;
+        st = setup_device(p);
+        if (st != VBW_OK) {
+            free_device(p);
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return VBW_OK;
+}
+
+vbw_status vbw_set_bandwidth(vbw_plan_t p, int32_t channel, int32_t k1, int64_t from_block) {
+    if (!p || channel < 0 || size_t(channel) >= p->ch.size() || from_block < 0) return VBW_EINVAL;
+    const vbw_channel &ch = p->ch[channel];
+    if (!k1_in_range(ch.n, ch.lv, k1)) return VBW_ERANGE;
+    auto &e = p->sched[channel].e;
+    auto it = std::lower_bound(e.begin(), e.end(), std::make_pair(from_block, INT32_MIN));
+    if (it != e.end() && it->first == from_block) {
+        it->second = k1;
+    } else {
+        if (int(e.size()) >= kMaxSchedPerChannel) return VBW_EINVAL;
+        try {
+            e.insert(it, {from_block, k1});
+        } catch (const std::bad_alloc &) {
+            return VBW_ENOMEM;
+        }
+    }
+    p->sched_dirty = true;
+    return VBW_OK;
+}
+
+vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *stream) {
+    if (!p || !x || !y) return VBW_EINVAL;
+    if (p->host_only) return VBW_EUNSUPPORTED;
+    if (!ranges_ok(p, x, y)) return VBW_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return from_hip(e);
+    if (prev != p->device && (e = hipSetDevice(p->device)) != hipSuccess) return from_hip(e);
+
+    vbw_status st = VBW_OK;
+    const size_t nch = p->ch.size();
+    const bool ptrs_same = p->dyn_valid && std::equal(x, x + nch, p->last_x.begin()) &&
+                           std::equal(y, y + nch, p->last_y.begin());
+    if (!ptrs_same || p->sched_dirty) st = upload_dyn(p, x, y, s);
+
+    if (st == VBW_OK && !p->items.empty()) {
+        if ((p->flags & VBW_GRAPH) && s != nullptr) {
+            if (!p->graph_exec) {
+                e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    hipError_t le = launch(p, p->cap_stream);
+                    e = hipStreamEndCapture(p->cap_stream, &p->graph);
+                    if (le != hipSuccess) e = le;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) st = from_hip(e);
+            }
+            if (st == VBW_OK) st = from_hip(hipGraphLaunch(p->graph_exec, s));
+        } else {
+            st = from_hip(launch(p, s));
+        }
+    }
+    if (st == VBW_OK) st = from_hip(hipEventRecord(p->done_evt, s));
+    if (prev != p->device) (void)hipSetDevice(prev);
+    return st;
+}
+
+void vbw_destroy(vbw_plan_t p) {
+    if (!p) return;
+    free_device(p);
+    delete p;
+}
+
+const char *vbw_strerror(vbw_status s) {
+    switch (s) {
+        case VBW_OK: return "success";
+        case VBW_EINVAL: return "invalid argument";
+        case VBW_ERANGE: return "band edge out of range";
+        case VBW_ENOMEM: return "out of memory";
+        case VBW_EDEVICE: return "device error";
+        case VBW_EUNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+int64_t vbw_plan_query(vbw_plan_t p, int32_t q) {
+    if (!p) return VBW_EINVAL;
+    switch (q) {
+        case VBW_Q_N_CHANNELS: return int64_t(p->ch.size());
+        case VBW_Q_N_ITEMS: return int64_t(p->items.size());
+        case VBW_Q_TOTAL_BLOCKS: return p->total_blocks;
+        case VBW_Q_TOTAL_SAMPLES: return p->total_samples;
+        case VBW_Q_WORKGROUP: return vbw::kThreads;
+        case VBW_Q_LDS_BYTES: return int64_t(vbw::kLdsValues * sizeof(float2));
+        case VBW_Q_GRID: return int64_t(p->items.size());
+        case VBW_Q_KERNEL_VARIANT: return p->variant;
+    }
+    return VBW_EINVAL;
+}
+
+int32_t vbw_block_k1(vbw_plan_t p, int32_t channel, int64_t block) {
+    if (!p || channel < 0 || size_t(channel) >= p->ch.size() || block < 0) return VBW_EINVAL;
+    int32_t k1 = VBW_EINVAL;
+    for (auto &pr : p->sched[channel].e)
+        if (pr.first <= block) k1 = pr.second;
+    return k1;
+}
+
+vbw_status vbw_twiddle_table(int32_t n, float *out) {
+    if (!out || !is_pow2(n) || n < 2 || n > vbw::kTwiddleN) return VBW_EINVAL;
+    fill_twiddles(n, out);
+    return VBW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// vbw_internal.h -- device-table layouts shared by the plan code and the
+// gfx950 kernels of the overlap-save variable-bandwidth filter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vbw {
+
+constexpr int kMaxLog2N = 12;            // N <= 4096
+constexpr int kMinLog2N = 4;             // N >= 16
+constexpr int kPointsPerThread = 16;     // every thread owns 16 complex values
+constexpr int kThreads = 256;            // workgroup size
+constexpr int kTilePoints = kThreads * kPointsPerThread;  // 4096 values per workgroup
+constexpr int kTwiddleN = 1 << kMaxLog2N;                 // one table of w_4096^r
+
+// LDS: one padded 4096-value tile; a pad slot after every 16 values.
+__host__ __device__ constexpr int lds_pad(int p) { return p + (p >> 4); }
+constexpr int kLdsValues = lds_pad(kTilePoints);
+
+// Per-channel constants (device table, 32 bytes).
+struct ChannelDev {
+    int64_t len;
+    int32_t n;
+    int32_t hop;
+    int32_t lv;
+    int32_t v_offset;
+    int32_t sched_begin;   // first schedule entry of this channel
+    int32_t sched_count;   // entries, sorted by from_block, first has from_block 0
+};
+
+// One bandwidth-schedule entry (16 bytes).
+struct SchedDev {
+    int64_t from_block;
+    int32_t k1;
+    int32_t pad;
+};
+
+// One workgroup's work: `n_blocks` consecutive blocks of one channel.
+// n_blocks <= 4096 / N so the blocks fill one 4096-value tile.
+struct WorkItem {
+    int32_t channel;
+    int32_t first_block;
+    int32_t n_blocks;
+    int32_t log2n;
+};
+
+enum class Storage : int { C64 = 0, F16 = 1, BF16 = 2 };
+
+struct LaunchArgs {
+    const WorkItem *items;
+    const ChannelDev *ch;
+    const SchedDev *sched;
+    const float *v;          // V pool, float32
+    const float2 *tw;        // w_4096^r, r < 4096
+    const void *const *x;    // per-channel input pointers
+    void *const *y;          // per-channel output pointers
+    int32_t n_items;
+    int32_t xcd_remap;       // nonzero: keep consecutive items on one XCD
+};
+
+// Host launchers (ols_fft.hip).  log2n_fixed = 0 selects the kernel that
+// dispatches on each item's N; otherwise every item must have that N.
+hipError_t launch_ols_fft(const LaunchArgs &args, int log2n_fixed, Storage in,
+                          bool f32_out, hipStream_t stream);
+
+}  // namespace vbw

@@ -1,0 +1,200 @@
+"""Python binding of ``libvbw.so`` (C ABI in ``include/vbw.h``).
+
+Argument marshalling only: every step of the filtering runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.  There is no CPU
+fallback: if the library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvbw.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vbw.h")
+
+VBW_OK, VBW_EINVAL, VBW_ERANGE, VBW_ENOMEM, VBW_EDEVICE, VBW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+DTYPES = {"c64": 0, "f16": 1, "bf16": 2}
+ENGINES = {"fft": 0, "gemm": 1}
+NO_PRUNE, GRAPH, F32_OUT, HOST_ONLY, AUTOTUNE = 1, 2, 4, 8, 16
+Q_N_CHANNELS, Q_N_ITEMS, Q_TOTAL_BLOCKS, Q_TOTAL_SAMPLES, Q_WORKGROUP, Q_LDS_BYTES, Q_GRID, Q_VARIANT = range(8)
+
+
+class vbw_channel(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("hop", ctypes.c_int32), ("lv", ctypes.c_int32),
+                ("v_offset", ctypes.c_int32), ("k1", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("len", ctypes.c_int64)]
+
+
+class vbw_plan_desc(ctypes.Structure):
+    _fields_ = [("n_channels", ctypes.c_int32), ("n_v", ctypes.c_int32),
+                ("channels", ctypes.POINTER(vbw_channel)), ("v_pool", ctypes.POINTER(ctypes.c_double)),
+                ("dtype", ctypes.c_int32), ("engine", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class VbwError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+_LIB = None
+
+
+def lib():
+    """Load libvbw.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the HIP library is the only compute path)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.vbw_plan.argtypes = [ctypes.POINTER(vbw_plan_desc), ctypes.POINTER(P)]
+        L.vbw_plan.restype = ctypes.c_int
+        L.vbw_set_bandwidth.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+        L.vbw_set_bandwidth.restype = ctypes.c_int
+        L.vbw_filter.argtypes = [P, P, P, P]
+        L.vbw_filter.restype = ctypes.c_int
+        L.vbw_destroy.argtypes = [P]
+        L.vbw_destroy.restype = None
+        L.vbw_strerror.argtypes = [ctypes.c_int]
+        L.vbw_strerror.restype = ctypes.c_char_p
+        L.vbw_plan_query.argtypes = [P, ctypes.c_int32]
+        L.vbw_plan_query.restype = ctypes.c_int64
+        L.vbw_block_k1.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
+        L.vbw_block_k1.restype = ctypes.c_int32
+        L.vbw_twiddle_table.argtypes = [ctypes.c_int32, P]
+        L.vbw_twiddle_table.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def header_functions() -> list:
+    """Names of the functions include/vbw.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vbw_[a-z0-9_]+)\s*\(", text)))
+
+
+def strerror(status: int) -> str:
+    return lib().vbw_strerror(int(status)).decode()
+
+
+def twiddle_table(n: int) -> np.ndarray:
+    out = np.empty(2 * n, dtype=np.float32)
+    rc = lib().vbw_twiddle_table(int(n), out.ctypes.data_as(ctypes.c_void_p))
+    if rc != VBW_OK:
+        raise VbwError(rc, "vbw_twiddle_table")
+    return out.reshape(n, 2)
+
+
+class Plan:
+    """One vbw_plan: channels, shared V pool, storage dtype, engine, flags.
+
+    ``channels`` is a sequence of dicts or objects with n, hop, lv, v_offset,
+    k1 and len (or ``length``).
+    """
+
+    def __init__(self, channels, v_pool, dtype: str = "c64", engine: str = "fft", flags: int = 0):
+        chans = list(channels)
+        self.n_channels = len(chans)
+        arr = (vbw_channel * max(1, len(chans)))()
+        self.lengths = []
+        for i, c in enumerate(chans):
+            g = (lambda k, c=c: c[k]) if isinstance(c, dict) else (lambda k, c=c: getattr(c, k))
+            length = c["len"] if isinstance(c, dict) else c.length
+            arr[i] = vbw_channel(int(g("n")), int(g("hop")), int(g("lv")), int(g("v_offset")),
+                                 int(g("k1")), 0, int(length))
+            self.lengths.append(int(length))
+        self.v_pool = np.ascontiguousarray(np.asarray(v_pool, dtype=np.float64))
+        self.dtype = dtype
+        self.flags = int(flags)
+        desc = vbw_plan_desc(len(chans), int(self.v_pool.size), arr,
+                             self.v_pool.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                             if self.v_pool.size else None,
+                             DTYPES[dtype], ENGINES[engine], self.flags, 0)
+        h = ctypes.c_void_p()
+        rc = lib().vbw_plan(ctypes.byref(desc), ctypes.byref(h))
+        if rc != VBW_OK:
+            raise VbwError(rc, "vbw_plan")
+        self._h = h
+        self._xp = (ctypes.c_void_p * max(1, len(chans)))()
+        self._yp = (ctypes.c_void_p * max(1, len(chans)))()
+
+    @classmethod
+    def from_workload(cls, w, dtype: str | None = None, engine: str = "fft", flags: int = 0):
+        pool, offs = w.v_pool()
+        chans = [dict(n=c.n, hop=c.hop, lv=c.lv, v_offset=offs[c.v_key], k1=c.k1, len=c.length)
+                 for c in w.channels]
+        if dtype is None:
+            dtype = {"c64": "c64", "c128": "c64", "f16": "f16", "bf16": "bf16"}[w.storage]
+        p = cls(chans, pool, dtype=dtype, engine=engine, flags=flags)
+        for i, c in enumerate(w.channels):
+            for frm, k1 in c.schedule:
+                p.set_bandwidth(i, k1, frm)
+        return p
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def set_bandwidth(self, channel: int, k1: int, from_block: int) -> None:
+        rc = lib().vbw_set_bandwidth(self.handle, int(channel), int(k1), int(from_block))
+        if rc != VBW_OK:
+            raise VbwError(rc, "vbw_set_bandwidth")
+
+    def filter_ptrs(self, x_ptrs, y_ptrs, stream: int | None = 0) -> None:
+        """Raw form: integer device addresses, integer hipStream_t (0 = null stream)."""
+        for i in range(self.n_channels):
+            self._xp[i] = x_ptrs[i] or None
+            self._yp[i] = y_ptrs[i] or None
+        rc = lib().vbw_filter(self.handle, ctypes.cast(self._xp, ctypes.c_void_p),
+                              ctypes.cast(self._yp, ctypes.c_void_p), stream or None)
+        if rc != VBW_OK:
+            raise VbwError(rc, "vbw_filter")
+
+    def filter(self, xs, ys, stream=None) -> None:
+        """Filter torch tensors: complex64 (c64 storage) or (len, 2) float16 /
+        bfloat16 (16-bit storage); outputs likewise, or (len, 2) float32 /
+        complex64 with F32_OUT.  Runs on ``stream`` (default: torch's current)."""
+        import torch
+        if len(xs) != self.n_channels or len(ys) != self.n_channels:
+            raise ValueError("one input and one output tensor per channel")
+        for t in list(xs) + list(ys):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous and on the GPU")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self.filter_ptrs([t.data_ptr() for t in xs], [t.data_ptr() for t in ys], s)
+
+    def query(self, q: int) -> int:
+        return int(lib().vbw_plan_query(self.handle, int(q)))
+
+    def block_k1(self, channel: int, block: int) -> int:
+        return int(lib().vbw_block_k1(self.handle, int(channel), int(block)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().vbw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False

@@ -1,0 +1,191 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every declared function, validation returns the documented codes,
+the integer planner and bandwidth schedule agree with an independent
+enumeration, and the float32 twiddle table is correctly rounded."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2406_14116_amd import vbw
+
+
+def chan(n=256, hop=192, lv=8, k1=24, length=65536, v_offset=0):
+    return dict(n=n, hop=hop, lv=lv, v_offset=v_offset, k1=k1, len=length)
+
+
+def host_plan(chans, v=None, **kw):
+    if v is None:
+        v = np.linspace(0.9, 0.1, 64)
+    return vbw.Plan(chans, v, flags=vbw.HOST_ONLY | kw.pop("flags", 0), **kw)
+
+
+def test_library_exports_every_declared_function():
+    names = vbw.header_functions()
+    assert {"vbw_plan", "vbw_set_bandwidth", "vbw_filter", "vbw_destroy", "vbw_strerror"} <= set(names)
+    L = vbw.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_strerror_codes():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert vbw.strerror(code) and vbw.strerror(code) != "unknown status"
+    assert vbw.strerror(-99) == "unknown status"
+
+
+@pytest.mark.parametrize("n", [2, 16, 256, 1024, 4096])
+def test_twiddle_table_correctly_rounded(n):
+    tw = vbw.twiddle_table(n).astype(np.float64)
+    r = np.arange(n)
+    ang = 2.0 * np.pi * r / n
+    exact = np.stack([np.cos(ang), -np.sin(ang)], axis=1)
+    # within half an ulp of float32 (plus the float64 reference's own error)
+    ulp = np.spacing(np.abs(exact).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(tw - exact) <= 0.5 * ulp + 4e-16)
+    # exact symmetries of the table
+    assert tw[0, 0] == 1.0 and tw[0, 1] == 0.0
+    if n >= 4:
+        assert tw[n // 4, 0] == 0.0 and tw[n // 4, 1] == -1.0
+        assert np.array_equal(tw[1:, 0], tw[1:, 0][::-1])
+        assert np.array_equal(tw[1:, 1], -tw[1:, 1][::-1])
+
+
+def test_twiddle_subtables_are_strided_views():
+    big = vbw.twiddle_table(4096)
+    for n in (16, 512):
+        assert np.array_equal(vbw.twiddle_table(n), big[:: 4096 // n])
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n=300), vbw.VBW_EINVAL),           # not a power of two
+    (dict(n=8, hop=6, k1=2, lv=1), vbw.VBW_EINVAL),   # N below 16
+    (dict(n=8192, hop=6144), vbw.VBW_EINVAL),  # N above 4096
+    (dict(hop=191), vbw.VBW_EINVAL),           # N - M odd: no integer delay
+    (dict(hop=256), vbw.VBW_EINVAL),           # M must be < N
+    (dict(hop=0), vbw.VBW_EINVAL),
+    (dict(lv=-1), vbw.VBW_EINVAL),
+    (dict(len=-5), vbw.VBW_EINVAL),
+    (dict(v_offset=60), vbw.VBW_EINVAL),       # V range outside the pool
+    (dict(k1=0), vbw.VBW_ERANGE),
+    (dict(k1=121), vbw.VBW_ERANGE),            # k2 = 128 = N/2
+    (dict(k1=130, lv=0), vbw.VBW_ERANGE),
+    (dict(k1=129, lv=1), vbw.VBW_ERANGE),
+])
+def test_validation_codes(bad, code):
+    c = chan()
+    c.update(bad)
+    with pytest.raises(vbw.VbwError) as e:
+        host_plan([c])
+    assert e.value.status == code
+
+
+def test_admissible_edges():
+    host_plan([chan(k1=129, lv=0)]).close()   # all-pass: every bin is passband
+    host_plan([chan(k1=120, lv=8)]).close()   # k2 = N/2 - 1
+    host_plan([chan(k1=1, lv=0)]).close()     # only the DC bin passes
+    host_plan([chan(length=0)]).close()       # empty channel
+
+
+def test_validation_of_descriptor_fields():
+    with pytest.raises(vbw.VbwError) as e:
+        host_plan([chan()], v=[0.5, float("nan")] + [0.1] * 20)
+    assert e.value.status == vbw.VBW_EINVAL
+    with pytest.raises(vbw.VbwError) as e:
+        host_plan([chan()], flags=1 << 20)
+    assert e.value.status == vbw.VBW_EINVAL
+    with pytest.raises(vbw.VbwError) as e:
+        host_plan([])
+    assert e.value.status == vbw.VBW_EINVAL
+    with pytest.raises(vbw.VbwError) as e:
+        host_plan([chan()], engine="gemm")    # float32 storage has no GEMM engine
+    assert e.value.status == vbw.VBW_EUNSUPPORTED
+
+
+def test_host_only_plan_refuses_to_filter():
+    p = host_plan([chan()])
+    with pytest.raises(vbw.VbwError) as e:
+        p.filter_ptrs([0x1000], [0x100000])
+    assert e.value.status == vbw.VBW_EUNSUPPORTED
+
+
+def enumerate_items(chans):
+    """Independent enumeration: ceil(len/M) blocks per channel, tiled into
+    groups of 4096/N consecutive blocks."""
+    items, blocks = [], 0
+    for ci, c in enumerate(chans):
+        nb = -(-c["len"] // c["hop"]) if c["len"] > 0 else 0
+        blocks += nb
+        per = 4096 // c["n"]
+        first = 0
+        while first < nb:
+            items.append((ci, first, min(per, nb - first)))
+            first += per
+    return items, blocks
+
+
+def test_planner_counts_match_enumeration():
+    rng = np.random.default_rng(0)
+    chans = []
+    for i in range(40):
+        n = int(2 ** rng.integers(4, 13))
+        hop = int(n - 2 * rng.integers(1, n // 2))
+        length = int(rng.choice([0, 1, hop - 1, hop, hop + 1, int(rng.integers(1, 50000))]))
+        lv = int(rng.integers(0, min(8, n // 2 - 1) + 1))
+        chans.append(chan(n=n, hop=hop, lv=lv, k1=1, length=max(0, length)))
+    p = host_plan(chans)
+    items, blocks = enumerate_items(chans)
+    assert p.query(vbw.Q_N_ITEMS) == len(items)
+    assert p.query(vbw.Q_TOTAL_BLOCKS) == blocks
+    assert p.query(vbw.Q_TOTAL_SAMPLES) == sum(c["len"] for c in chans)
+    assert p.query(vbw.Q_N_CHANNELS) == 40
+    assert p.query(vbw.Q_WORKGROUP) == 256
+
+
+def test_schedule_semantics():
+    """Block m uses the entry with the largest from_block <= m; an equal
+    from_block replaces; a failed call changes nothing."""
+    p = host_plan([chan(), chan(k1=30)])
+    p.set_bandwidth(0, 40, 512)
+    p.set_bandwidth(0, 50, 100)
+    p.set_bandwidth(0, 60, 512)          # replaces (512, 40)
+    expect = {0: 24, 99: 24, 100: 50, 511: 50, 512: 60, 10 ** 6: 60}
+    for m, k1 in expect.items():
+        assert p.block_k1(0, m) == k1
+    assert p.block_k1(1, 5000) == 30
+    for args, code in [((0, 0, 10), vbw.VBW_ERANGE), ((0, 121, 10), vbw.VBW_ERANGE),
+                       ((2, 30, 0), vbw.VBW_EINVAL), ((0, 30, -1), vbw.VBW_EINVAL)]:
+        with pytest.raises(vbw.VbwError) as e:
+            p.set_bandwidth(*args)
+        assert e.value.status == code
+    for m, k1 in expect.items():
+        assert p.block_k1(0, m) == k1
+    p.set_bandwidth(0, 33, 0)            # replaces the initial edge
+    assert p.block_k1(0, 0) == 33 and p.block_k1(0, 512) == 60
+    assert p.block_k1(0, -1) == vbw.VBW_EINVAL
+
+
+def test_schedule_matches_oracle_rule():
+    """Random schedules: the library's lookup equals the oracle's rule applied
+    by plain Python (largest from_block <= m, later duplicates win)."""
+    rng = np.random.default_rng(1)
+    p = host_plan([chan(n=1024, hop=768, lv=16, k1=30, length=1 << 20)])
+    entries = [(0, 30)]
+    for _ in range(50):
+        frm, k1 = int(rng.integers(0, 1400)), int(rng.integers(1, 496))
+        p.set_bandwidth(0, k1, frm)
+        entries.append((frm, k1))
+    for m in range(0, 1400, 7):
+        # the last call among those with the largest from_block <= m
+        cands = [(frm, i, k1) for i, (frm, k1) in enumerate(entries) if frm <= m]
+        want = max(cands)[2]
+        assert p.block_k1(0, m) == want
+
+
+def test_plan_copies_descriptors():
+    chans = [chan()]
+    v = np.linspace(0.9, 0.1, 64)
+    p = vbw.Plan(chans, v, flags=vbw.HOST_ONLY)
+    v[:] = 0.0
+    chans[0]["len"] = 1
+    assert p.query(vbw.Q_TOTAL_SAMPLES) == 65536
