@@ -171,6 +171,14 @@ int32_t vbw_block_k1(vbw_plan_t plan, int32_t channel, int64_t block);
  * convention: exp(-j 2 pi r / n)). */
 vbw_status vbw_twiddle_table(int32_t n, float *out);
 
+/* Streaming device-to-device copy of `bytes` bytes on `stream`, used to
+ * measure the achievable HBM bandwidth that the filter is compared with
+ * (a plain copy moves exactly the filter's algorithmic bytes per sample).
+ * src and dst are device pointers, 16-byte aligned, non-overlapping.
+ * Errors: VBW_EINVAL (misaligned, overlapping, NULL with bytes > 0,
+ * bytes < 0); VBW_EDEVICE from HIP. */
+vbw_status vbw_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

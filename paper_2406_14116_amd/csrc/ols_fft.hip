@@ -27,15 +27,17 @@
 
 #include "vbw_internal.h"
 
+#ifndef VBW_PREFETCH
+#define VBW_PREFETCH 0
+#endif
+#ifndef VBW_WAVES_PER_EU
+#define VBW_WAVES_PER_EU 3
+#endif
+
 namespace vbw {
 namespace {
 
 typedef float f2v __attribute__((ext_vector_type(2)));
-// Channel buffers are plain device allocations: address them as global memory
-// (address space 1) so loads and stores use the global, not the flat, path.
-#define VBW_GLOBAL __attribute__((address_space(1)))
-typedef VBW_GLOBAL f2v gf2v;
-typedef VBW_GLOBAL uint32_t gu32;
 
 // ---------------------------------------------------------------- complex ops
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -165,12 +167,27 @@ template <int R, bool INV> __device__ __forceinline__ void dft_small(float2 (&a)
 }
 
 // ------------------------------------------------------------ storage
+// Channel data is read and written through buffer resources: 32-bit byte
+// offsets from a per-item base, and the hardware range check (offset >=
+// num_records reads 0 and drops stores) provides the zero fill past the end
+// of the input and the truncation of the last output block.
+constexpr int kBufFlags = 0x00020000;   // raw buffer, 32-bit dword format
+constexpr int kNT = 2;                  // non-temporal cache policy: streamed once
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int64_t bytes) {
+    const int64_t cap = 0x7ffff000;     // every offset used stays far below
+    const int n = int(bytes <= 0 ? 0 : (bytes < cap ? bytes : cap));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, n, kBufFlags);
+}
+
 template <Storage S> struct Io;
 
 template <> struct Io<Storage::C64> {
-    __device__ static float2 ld(const void *base, int64_t i) {
-        const f2v v = __builtin_nontemporal_load((const gf2v *)base + i);
-        return make_float2(v.x, v.y);
+    static constexpr int kBytes = 8;
+    __device__ static float2 ld(__amdgpu_buffer_rsrc_t r, int off) {
+        const u2v u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kNT);
+        return make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
     }
 };
 
@@ -181,31 +198,34 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
 }
 
 template <> struct Io<Storage::F16> {
-    __device__ static float2 ld(const void *base, int64_t i) {
-        const uint32_t u = __builtin_nontemporal_load((const gu32 *)base + i);
-        const __half2 h = __builtin_bit_cast(__half2, u);
-        return __half22float2(h);
+    static constexpr int kBytes = 4;
+    __device__ static float2 ld(__amdgpu_buffer_rsrc_t r, int off) {
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kNT);
+        return __half22float2(__builtin_bit_cast(__half2, u));
     }
 };
 
 template <> struct Io<Storage::BF16> {
-    __device__ static float2 ld(const void *base, int64_t i) {
-        const uint32_t u = __builtin_nontemporal_load((const gu32 *)base + i);
+    static constexpr int kBytes = 4;
+    __device__ static float2 ld(__amdgpu_buffer_rsrc_t r, int off) {
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kNT);
         return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
     }
 };
 
-template <Storage S, bool F32OUT> __device__ __forceinline__ void st(void *base, int64_t i, float2 v) {
-    if constexpr (S == Storage::C64 || F32OUT) {
-        __builtin_nontemporal_store(f2v{v.x, v.y}, (gf2v *)base + i);
-    } else if constexpr (S == Storage::F16) {
-        const __half2 h = __float22half2_rn(v);
-        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, h), (gu32 *)base + i);
-    } else {
-        const uint32_t u = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
-        __builtin_nontemporal_store(u, (gu32 *)base + i);
+template <Storage S, bool F32OUT> struct Out {
+    static constexpr int kBytes = (S == Storage::C64 || F32OUT) ? 8 : 4;
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
+        if constexpr (kBytes == 8) {
+            __builtin_amdgcn_raw_buffer_store_b64(u2v{__float_as_uint(v.x), __float_as_uint(v.y)}, r, off, 0, kNT);
+        } else if constexpr (S == Storage::F16) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __float22half2_rn(v)), r, off, 0, kNT);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16), r, off, 0,
+                                                  kNT);
+        }
     }
-}
+};
 
 // ------------------------------------------------------------ tile sync
 // A team of <= 64 threads lives in one wave: LDS accesses of one wave are
@@ -233,53 +253,83 @@ template <int LOG2N> struct Shape {
     static constexpr int TWS = kTwiddleN / N;        // table stride of w_N
 };
 
-__device__ __forceinline__ float2 twiddle(const float2 *__restrict__ tw, int idx) { return tw[idx]; }
+// Twiddle table w_4096^r through a buffer resource: 32-bit byte offsets.
+struct Tw {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ float2 operator()(unsigned idx) const {
+        const u2v u = __builtin_amdgcn_raw_buffer_load_b64(r, int(idx * 8u), 0, 0);
+        return make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
+    }
+};
 
-// Middle radix-16 pass Q (2 <= Q, not the last): Ns = 16^(Q-1).
-// Forward: gather t + T r, twiddle w_{16 Ns}^{j r} (j = t mod Ns), DFT,
-// scatter to (t/Ns) 16 Ns + j + Ns s.
-template <int LOG2N, int Q, bool INV>
-__device__ __forceinline__ void mid_pass(float2 (&a)[16], float2 *L, int t, const float2 *__restrict__ tw) {
+// The twiddles one thread applies depend only on its index t within the team
+// and on N, so a workgroup loads them once into registers and reuses them for
+// every block it filters, forward (as is) and inverse (conjugated).
+//   mid:  middle pass (Ns = 16, only when N >= 512): w_256^{(t mod 16) r}, r = 1..15
+//   last: last pass, butterfly b = t + T u: w_N^{b r}, r = 1..R-1
+template <int LOG2N> struct TwReg {
     using Sh = Shape<LOG2N>;
-    constexpr int NS = 1 << (4 * (Q - 1));
-    constexpr int STRIDE = kTwiddleN / (16 * NS);
-    const int j = t & (NS - 1);
-    const int sbase = (t / NS) * NS * 16 + j;
+    static constexpr int R = Sh::RLAST;
+    static constexpr int U = 16 / R;
+    static constexpr bool kMid = Sh::NP == 3;
+    static constexpr bool kLast = Sh::NP > 1;
+    float2 mid[kMid ? 15 : 1];
+    float2 last[kLast ? U * (R - 1) : 1];
+
+    __device__ void load(const Tw &tw, int t) {
+        static_assert(Sh::NP <= 3, "N <= 4096");
+        if constexpr (kMid) {
+            const unsigned j = unsigned(t) & 15u;
+#pragma unroll
+            for (int r = 1; r < 16; ++r) mid[r - 1] = tw(16u * j * unsigned(r));
+        }
+        if constexpr (kLast) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned b = unsigned(t + Sh::T * u);
+#pragma unroll
+                for (int r = 1; r < R; ++r) last[u * (R - 1) + r - 1] = tw(Sh::TWS * b * unsigned(r));
+            }
+        }
+    }
+};
+
+// LDS slot of stride-layout value t + T r (T a multiple of 16 splits the pad).
+template <int T> __device__ __forceinline__ int lds_stride_pos(int t, int r) {
+    if constexpr (T % 16 == 0) return lds_pad(t) + r * (T + T / 16);
+    else return lds_pad(t + T * r);
+}
+
+// Middle radix-16 pass (pass 2 of 3, Ns = 16).
+// Forward: gather t + T r, twiddle w_256^{j r} (j = t mod 16), DFT, scatter
+// to (t/16) 256 + j + 16 s.  Inverse: the adjoint, in reverse order.
+template <int LOG2N, bool INV>
+__device__ __forceinline__ void mid_pass(float2 (&a)[16], float2 *L, int t, const TwReg<LOG2N> &tw) {
+    using Sh = Shape<LOG2N>;
+    constexpr int NS = 16;
+    const int sbase = (t / NS) * NS * 16 + (t & (NS - 1));
+    const int sb = lds_pad(sbase);           // (sbase + 16 s) pads to sb + 17 s
+    constexpr int SSTEP = NS + NS / 16;
     if constexpr (!INV) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) a[r] = L[lds_pad(t + Sh::T * r)];
+        for (int r = 0; r < 16; ++r) a[r] = L[lds_stride_pos<Sh::T>(t, r)];
 #pragma unroll
-        for (int r = 1; r < 16; ++r) a[r] = cmul(a[r], twiddle(tw, STRIDE * j * r));
+        for (int r = 1; r < 16; ++r) a[r] = cmul(a[r], tw.mid[r - 1]);
         dft16<false>(a);
         tile_sync<Sh::WAVE_LOCAL>();
 #pragma unroll
-        for (int s = 0; s < 16; ++s) L[lds_pad(sbase + NS * s)] = a[s];
+        for (int s = 0; s < 16; ++s) L[sb + SSTEP * s] = a[s];
         tile_sync<Sh::WAVE_LOCAL>();
     } else {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) a[s] = L[lds_pad(sbase + NS * s)];
+        for (int s = 0; s < 16; ++s) a[s] = L[sb + SSTEP * s];
         dft16<true>(a);
 #pragma unroll
-        for (int r = 1; r < 16; ++r) a[r] = cmulc(a[r], twiddle(tw, STRIDE * j * r));
+        for (int r = 1; r < 16; ++r) a[r] = cmulc(a[r], tw.mid[r - 1]);
         tile_sync<Sh::WAVE_LOCAL>();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) L[lds_pad(t + Sh::T * r)] = a[r];
+        for (int r = 0; r < 16; ++r) L[lds_stride_pos<Sh::T>(t, r)] = a[r];
         tile_sync<Sh::WAVE_LOCAL>();
-    }
-}
-
-template <int LOG2N, int Q, bool INV>
-__device__ __forceinline__ void mid_passes(float2 (&a)[16], float2 *L, int t, const float2 *__restrict__ tw) {
-    using Sh = Shape<LOG2N>;
-    constexpr int LASTMID = Sh::NP - 1;   // passes 2 .. NP-1 are middle passes
-    if constexpr (Q <= LASTMID) {
-        if constexpr (!INV) {
-            mid_pass<LOG2N, Q, false>(a, L, t, tw);
-            mid_passes<LOG2N, Q + 1, false>(a, L, t, tw);
-        } else {
-            mid_passes<LOG2N, Q + 1, true>(a, L, t, tw);
-            mid_pass<LOG2N, Q, true>(a, L, t, tw);
-        }
     }
 }
 
@@ -288,164 +338,295 @@ __device__ __forceinline__ void mid_passes(float2 (&a)[16], float2 *L, int t, co
 // X(b + (N/R) s) in slots u + (16/R) s.  For N = 16 this is the only pass and
 // has no twiddle.
 template <int LOG2N, bool INV>
-__device__ __forceinline__ void last_pass(float2 (&a)[16], int t, const float2 *__restrict__ tw) {
+__device__ __forceinline__ void last_pass(float2 (&a)[16], const TwReg<LOG2N> &tw) {
     using Sh = Shape<LOG2N>;
     constexpr int R = Sh::RLAST;
     constexpr int U = 16 / R;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int b = t + Sh::T * u;
         float2 c[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) c[r] = a[u + U * r];
         if constexpr (!INV && Sh::NP > 1) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) c[r] = cmul(c[r], twiddle(tw, Sh::TWS * b * r));
+            for (int r = 1; r < R; ++r) c[r] = cmul(c[r], tw.last[u * (R - 1) + r - 1]);
         }
         dft_small<R, INV>(c);
         if constexpr (INV && Sh::NP > 1) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) c[r] = cmulc(c[r], twiddle(tw, Sh::TWS * b * r));
+            for (int r = 1; r < R; ++r) c[r] = cmulc(c[r], tw.last[u * (R - 1) + r - 1]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) a[u + U * r] = c[r];
     }
 }
 
-// H_R of eq. (6) with the mirror H_R(N-k) = H_R(k), times 1/N.
-// Slot v holds bin k = t + T v.
+// Step 3: Y(k) = H_R(k) X(k) / N (eq. (6), mirror H_R(N-k) = H_R(k)).  Slot v
+// holds bin k = t + T v; its mirrored index kk = min(k, N-k) is t + T v for
+// v < 8 and N - T v - t for v >= 8.  When every lane of the wave uses the same
+// k1, whole slots that are pure passband or pure stopband are decided by a
+// scalar test; only slots that meet the transition band read V.
 template <int LOG2N>
-__device__ __forceinline__ void hfso_multiply(float2 (&a)[16], int t, int k1, int lv,
-                                              const float *__restrict__ vv) {
+__device__ __forceinline__ void hfso_multiply(float2 (&a)[16], int t, int k1, int lv, const float *vl) {
     using Sh = Shape<LOG2N>;
-    constexpr float inv_n = 1.0f / float(Sh::N);
+    constexpr int N = Sh::N, T = Sh::T;
+    constexpr float inv_n = 1.0f / float(N);
+    const int k1u = __builtin_amdgcn_readfirstlane(k1);
+    if (__all(k1 == k1u)) {
+        const int k2u = k1u + lv - 1;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int k = t + Sh::T * v;
-        const int kk = (k <= Sh::N / 2) ? k : Sh::N - k;
-        const int jj = kk - k1;
-        float f = (jj < 0) ? inv_n : 0.0f;
-        if (jj >= 0 && jj < lv) f = vv[jj] * inv_n;
-        a[v].x *= f;
-        a[v].y *= f;
+        for (int v = 0; v < 16; ++v) {
+            const int lo = (v < 8) ? T * v : N - T * v - (T - 1);
+            const int hi = (v < 8) ? T * v + (T - 1) : N - T * v;
+            if (hi < k1u) {
+                a[v].x *= inv_n;
+                a[v].y *= inv_n;
+            } else if (lo > k2u) {
+                a[v] = make_float2(0.f, 0.f);
+            } else {
+                const int kk = (v < 8) ? t + T * v : N - T * v - t;
+                float f = (kk < k1u) ? inv_n : 0.0f;
+                if (lo <= k2u && hi >= k1u) {
+                    const int jj = kk - k1u;
+                    if (jj >= 0 && jj < lv) f = vl[jj] * inv_n;
+                }
+                a[v].x *= f;
+                a[v].y *= f;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int kk = (v < 8) ? t + T * v : N - T * v - t;
+            const int jj = kk - k1;
+            float f = (jj < 0) ? inv_n : 0.0f;
+            if (jj >= 0 && jj < lv) f = vl[jj] * inv_n;
+            a[v].x *= f;
+            a[v].y *= f;
+        }
     }
 }
 
-template <int LOG2N, Storage S, bool F32OUT>
-__device__ __forceinline__ void process_item(const LaunchArgs &A, const WorkItem &it, float2 *lds) {
+// Work items and channel descriptors are workgroup-uniform: index them with
+// values the compiler knows to be uniform so they come in by scalar loads and
+// never wait behind the vector-memory queue of in-flight channel data.
+// The tables are read-only for the whole launch, so they are read through the
+// constant address space.
+template <typename T> __device__ __forceinline__ T ld_uniform(const T *p, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) T cT;
+    return ((cT *)p)[__builtin_amdgcn_readfirstlane(i)];
+#else
+    return p[i];   // host pass: never executed
+#endif
+}
+__device__ __forceinline__ WorkItem load_item(const LaunchArgs &A, int i) { return ld_uniform(A.items, i); }
+__device__ __forceinline__ ChannelDev load_channel(const LaunchArgs &A, int c) { return ld_uniform(A.ch, c); }
+
+// Step 1: gather segment [m hop - (N - hop), m hop + hop) of block
+// m = first_block + team into slots v = t + T v.  One code path for every
+// item: samples before 0 (the zero history of the first blocks) get an
+// offset past the resource's end and read as 0, like samples past len.
+constexpr int kOutOfRange = int(0x80000000u);
+
+template <int LOG2N, Storage S>
+__device__ __forceinline__ void gather(float2 (&a)[16], const LaunchArgs &A, const WorkItem &it,
+                                       const ChannelDev &cd, int team, int t) {
     using Sh = Shape<LOG2N>;
     constexpr int N = Sh::N, T = Sh::T;
+    constexpr int EI = Io<S>::kBytes;
+    const int hop = cd.hop;
+    const int64_t base_item = int64_t(it.first_block) * hop - (N - hop);
+    const int64_t clip = base_item > 0 ? base_item : 0;
+    const char *xc = static_cast<const char *>(ld_uniform(A.x, it.channel));
+    const auto xr = make_rsrc(xc + clip * EI, (cd.len - clip) * EI);
+    const int j0 = int(base_item - clip) + team * hop + t;   // index relative to the resource
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int j = j0 + T * v;
+        a[v] = Io<S>::ld(xr, j >= 0 ? j * EI : kOutOfRange);
+    }
+}
+
+constexpr int kVCap = 2048;  // transition values staged in LDS (L_V <= N/2 <= 2048)
+
+struct WgState {
+    int v_offset = -1;   // V set currently staged in LDS
+    int lv = -1;
+};
+
+// Steps 2-5 for the blocks of one item, data already gathered into a.
+template <int LOG2N, Storage S, bool F32OUT>
+__device__ __forceinline__ void filter_item(float2 (&a)[16], const LaunchArgs &A, const WorkItem &it,
+                                            const ChannelDev &cd, const TwReg<LOG2N> &tw, float2 *lds,
+                                            float *vlds, WgState &ws) {
+    using Sh = Shape<LOG2N>;
+    constexpr int N = Sh::N, T = Sh::T;
+    constexpr int EO = Out<S, F32OUT>::kBytes;
     const int tid = threadIdx.x;
     const int team = tid / T;
     const int t = tid - team * T;
     float2 *L = lds + team * lds_pad(N);
-
-    const ChannelDev cd = A.ch[it.channel];
-    const int64_t m = int64_t(it.first_block) + team;
-    const bool active = team < it.n_blocks;
     const int hop = cd.hop;
     const int d = (N - hop) >> 1;
+    const int64_t m = int64_t(it.first_block) + team;
+    const bool active = team < it.n_blocks;
 
-    // k1 in force for block m: last schedule entry with from_block <= m
-    int k1 = A.sched[cd.sched_begin].k1;
-    for (int e = 1; e < cd.sched_count; ++e) {
-        const SchedDev sd = A.sched[cd.sched_begin + e];
-        if (sd.from_block <= m) k1 = sd.k1;
+    // stage this channel's V in LDS (workgroup-uniform decision)
+    if (cd.v_offset != ws.v_offset || cd.lv != ws.lv) {
+        __syncthreads();
+        for (int i = tid; i < cd.lv; i += kThreads) vlds[i] = A.v[cd.v_offset + i];
+        __syncthreads();
+        ws.v_offset = cd.v_offset;
+        ws.lv = cd.lv;
     }
 
-    // step 1: gather the segment [m hop - (N - hop), m hop + hop)
-    float2 a[16];
-    const int64_t base = m * hop - (N - hop);
-    const void *x = A.x[it.channel];
-    if (active && base >= 0 && base + N <= cd.len) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) a[v] = Io<S>::ld(x, base + t + T * v);
-    } else {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int64_t i = base + t + T * v;
-            a[v] = (active && i >= 0 && i < cd.len) ? Io<S>::ld(x, i) : make_float2(0.f, 0.f);
-        }
+    // k1 in force for block m: last schedule entry with from_block <= m
+    // (entries are read with scalar loads; only the comparison is per team)
+    int k1 = ld_uniform(A.sched, cd.sched_begin).k1;
+    for (int e = 1; e < cd.sched_count; ++e) {
+        const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
+        if (sd.from_block <= m) k1 = sd.k1;
     }
 
     // step 2: forward DFT
     if constexpr (Sh::NP == 1) {
-        last_pass<LOG2N, false>(a, t, A.tw);
+        last_pass<LOG2N, false>(a, tw);
     } else {
         dft16<false>(a);                                  // pass 1, Ns = 1
 #pragma unroll
-        for (int s = 0; s < 16; ++s) L[lds_pad(16 * t + s)] = a[s];
+        for (int s = 0; s < 16; ++s) L[17 * t + s] = a[s];
         tile_sync<Sh::WAVE_LOCAL>();
-        mid_passes<LOG2N, 2, false>(a, L, t, A.tw);
+        if constexpr (Sh::NP == 3) mid_pass<LOG2N, false>(a, L, t, tw);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) a[v] = L[lds_pad(t + T * v)];
-        last_pass<LOG2N, false>(a, t, A.tw);
+        for (int v = 0; v < 16; ++v) a[v] = L[lds_stride_pos<T>(t, v)];
+        last_pass<LOG2N, false>(a, tw);
     }
 
     // step 3: H_R and 1/N
-    hfso_multiply<LOG2N>(a, t, k1, cd.lv, A.v + cd.v_offset);
+    hfso_multiply<LOG2N>(a, t, k1, cd.lv, vlds);
 
     // step 4: inverse DFT (adjoint passes)
-    last_pass<LOG2N, true>(a, t, A.tw);
+    last_pass<LOG2N, true>(a, tw);
     if constexpr (Sh::NP > 1) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) L[lds_pad(t + T * v)] = a[v];
+        for (int v = 0; v < 16; ++v) L[lds_stride_pos<T>(t, v)] = a[v];
         tile_sync<Sh::WAVE_LOCAL>();
-        mid_passes<LOG2N, 2, true>(a, L, t, A.tw);
+        if constexpr (Sh::NP == 3) mid_pass<LOG2N, true>(a, L, t, tw);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) a[s] = L[lds_pad(16 * t + s)];
+        for (int s = 0; s < 16; ++s) a[s] = L[17 * t + s];
         dft16<true>(a);
     }
 
-    // step 5: keep z0(D + j), j < hop, within len
+    // step 5: keep z0(D + j), j < hop; stores past len are dropped by the
+    // buffer range check
     if (active) {
-        void *y = A.y[it.channel];
-        const int64_t obase = m * hop;
+        const int64_t obase = int64_t(it.first_block) * hop;
+        const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, it.channel)) + obase * EO,
+                                  (cd.len - obase) * EO);
+        const int o0 = team * hop + t - d;   // output index of slot 0, may be < 0
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int j = t + T * v - d;
-            if (unsigned(j) < unsigned(hop) && obase + j < cd.len) st<S, F32OUT>(y, obase + j, a[v]);
+            const int j = t + T * v - d;        // index within the block's kept samples
+            Out<S, F32OUT>::st(yr, unsigned(j) < unsigned(hop) ? (o0 + T * v) * EO : kOutOfRange, a[v]);
         }
     }
 }
 
-__device__ __forceinline__ int item_index(const LaunchArgs &A) {
-    int wg = blockIdx.x;
-    if (A.xcd_remap) {
-        // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-        // contiguous run of items so neighbouring blocks share its L2.
-        const int nwg = gridDim.x, q = nwg >> 3, r = nwg & 7;
-        const int xcd = wg & 7, idx = wg >> 3;
-        wg = xcd * q + min(xcd, r) + idx;
-    }
-    return wg;
-}
-
+// Consecutive items [i, end) of size N: twiddles loaded once, and the next
+// item's input is requested before the current one is filtered so its
+// latency hides behind the arithmetic.  Returns the first index not done.
 template <int LOG2N, Storage S, bool F32OUT>
-__global__ __launch_bounds__(kThreads) void ols_fft_kernel(const LaunchArgs A) {
-    __shared__ float2 lds[kLdsValues];
-    const WorkItem it = A.items[item_index(A)];
-    if constexpr (LOG2N != 0) {
-        process_item<LOG2N, S, F32OUT>(A, it, lds);
-    } else {
-        switch (it.log2n) {
-            case 4: process_item<4, S, F32OUT>(A, it, lds); break;
-            case 5: process_item<5, S, F32OUT>(A, it, lds); break;
-            case 6: process_item<6, S, F32OUT>(A, it, lds); break;
-            case 7: process_item<7, S, F32OUT>(A, it, lds); break;
-            case 8: process_item<8, S, F32OUT>(A, it, lds); break;
-            case 9: process_item<9, S, F32OUT>(A, it, lds); break;
-            case 10: process_item<10, S, F32OUT>(A, it, lds); break;
-            case 11: process_item<11, S, F32OUT>(A, it, lds); break;
-            case 12: process_item<12, S, F32OUT>(A, it, lds); break;
-            default: break;
+__device__ int run_items(const LaunchArgs &A, int i, int end, float2 *lds, float *vlds, WgState &ws) {
+    using Sh = Shape<LOG2N>;
+    const int tid = threadIdx.x;
+    const int team = tid / Sh::T;
+    const int t = tid - team * Sh::T;
+    TwReg<LOG2N> tw;
+    tw.load(Tw{make_rsrc(A.tw, int64_t(kTwiddleN) * 8)}, t);
+
+    WorkItem it = load_item(A, i);
+    ChannelDev cd = load_channel(A, it.channel);
+#if VBW_PREFETCH
+    // two register sets take turns: while one item is filtered the next
+    // item's input is in flight into the other (no copies between them)
+    float2 xa[16], xb[16];
+    gather<LOG2N, S>(xa, A, it, cd, team, t);
+    for (;;) {
+        int in = i + 1;
+        bool more = in < end && load_item(A, in).log2n == LOG2N;
+        WorkItem itb = it;
+        ChannelDev cdb = cd;
+        if (more) {
+            itb = load_item(A, in);
+            cdb = load_channel(A, itb.channel);
+            gather<LOG2N, S>(xb, A, itb, cdb, team, t);
         }
+        filter_item<LOG2N, S, F32OUT>(xa, A, it, cd, tw, lds, vlds, ws);
+        if (!more) return in;
+        i = in;
+        in = i + 1;
+        more = in < end && load_item(A, in).log2n == LOG2N;
+        if (more) {
+            it = load_item(A, in);
+            cd = load_channel(A, it.channel);
+            gather<LOG2N, S>(xa, A, it, cd, team, t);
+        }
+        filter_item<LOG2N, S, F32OUT>(xb, A, itb, cdb, tw, lds, vlds, ws);
+        if (!more) return in;
+        i = in;
+    }
+#else
+    float2 cur[16];
+    for (;;) {
+        gather<LOG2N, S>(cur, A, it, cd, team, t);
+        filter_item<LOG2N, S, F32OUT>(cur, A, it, cd, tw, lds, vlds, ws);
+        const int in = i + 1;
+        if (!(in < end && load_item(A, in).log2n == LOG2N)) return in;
+        i = in;
+        it = load_item(A, i);
+        cd = load_channel(A, it.channel);
+    }
+#endif
+}
+
+// Persistent launch: workgroup w filters items [wg_begin[w], wg_begin[w+1]),
+// a contiguous, cost-balanced range (consecutive blocks of a channel stay on
+// one CU, so the overlap each block re-reads is still in its caches).
+template <int LOG2N, Storage S, bool F32OUT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(VBW_WAVES_PER_EU, 8)))
+void ols_fft_kernel(const LaunchArgs A) {
+    __shared__ float2 lds[kLdsValues];
+    __shared__ float vlds[kVCap];
+    WgState ws;
+    const int w = blockIdx.x;
+    int i = ld_uniform(A.wg_begin, w);
+    const int end = ld_uniform(A.wg_begin, w + 1);
+    while (i < end) {
+        if constexpr (LOG2N != 0) {
+            i = run_items<LOG2N, S, F32OUT>(A, i, end, lds, vlds, ws);
+        } else {
+            switch (load_item(A, i).log2n) {
+                case 4: i = run_items<4, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 5: i = run_items<5, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 6: i = run_items<6, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 7: i = run_items<7, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 8: i = run_items<8, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 9: i = run_items<9, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 10: i = run_items<10, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 11: i = run_items<11, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 12: i = run_items<12, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                default: i = end; break;
+            }
+        }
+        // a change of N changes the LDS layout: let every team finish first
+        __syncthreads();
     }
 }
 
 template <Storage S, bool F32OUT>
 hipError_t launch_typed(const LaunchArgs &A, int log2n, hipStream_t stream) {
-    const dim3 grid(A.n_items), block(kThreads);
+    const dim3 grid(A.n_wg), block(kThreads);
     switch (log2n) {
         case 0: hipLaunchKernelGGL((ols_fft_kernel<0, S, F32OUT>), grid, block, 0, stream, A); break;
         case 4: hipLaunchKernelGGL((ols_fft_kernel<4, S, F32OUT>), grid, block, 0, stream, A); break;
@@ -462,7 +643,39 @@ hipError_t launch_typed(const LaunchArgs &A, int log2n, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <Storage S, bool F32OUT> int occupancy_typed(int log2n) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (log2n) {
+        case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<0, S, F32OUT>, kThreads, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<4, S, F32OUT>, kThreads, 0); break;
+        case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<5, S, F32OUT>, kThreads, 0); break;
+        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<6, S, F32OUT>, kThreads, 0); break;
+        case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<7, S, F32OUT>, kThreads, 0); break;
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<8, S, F32OUT>, kThreads, 0); break;
+        case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<9, S, F32OUT>, kThreads, 0); break;
+        case 10: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<10, S, F32OUT>, kThreads, 0); break;
+        case 11: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<11, S, F32OUT>, kThreads, 0); break;
+        case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ols_fft_kernel<12, S, F32OUT>, kThreads, 0); break;
+        default: break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 }  // namespace
+
+int ols_fft_wg_per_cu(int log2n_fixed, Storage in, bool f32_out) {
+    switch (in) {
+        case Storage::C64: return occupancy_typed<Storage::C64, false>(log2n_fixed);
+        case Storage::F16:
+            return f32_out ? occupancy_typed<Storage::F16, true>(log2n_fixed)
+                           : occupancy_typed<Storage::F16, false>(log2n_fixed);
+        case Storage::BF16:
+            return f32_out ? occupancy_typed<Storage::BF16, true>(log2n_fixed)
+                           : occupancy_typed<Storage::BF16, false>(log2n_fixed);
+    }
+    return 1;
+}
 
 hipError_t launch_ols_fft(const LaunchArgs &A, int log2n_fixed, Storage in, bool f32_out,
                           hipStream_t stream) {

@@ -118,6 +118,8 @@ struct vbw_plan_s {
     bool host_only = true;
     int device = 0;
     WorkItem *d_items = nullptr;
+    int32_t *d_wg_begin = nullptr;
+    std::vector<int32_t> wg_begin;   // persistent launch: items of workgroup w
     float *d_v = nullptr;
     float2 *d_tw = nullptr;
     unsigned char *d_dyn = nullptr;   // ChannelDev[nch] | x[nch] | y[nch] | SchedDev[cap]
@@ -204,6 +206,27 @@ void build_items(vbw_plan_s *p) {
     p->log2n_fixed = (uniform && first_log2 > 0) ? first_log2 : 0;
 }
 
+// Split the item list into n_wg contiguous ranges of equal estimated cost.
+// A workgroup always works through a whole 4096-value tile, so an item costs
+// about log2(N) FFT passes plus a fixed part for loads, multiply and stores.
+void partition_items(vbw_plan_s *p, int n_wg) {
+    const size_t n = p->items.size();
+    std::vector<double> pre(n + 1, 0.0);
+    for (size_t i = 0; i < n; ++i) pre[i + 1] = pre[i] + (p->items[i].log2n + 2.0);
+    p->wg_begin.assign(size_t(n_wg) + 1, 0);
+    size_t i = 0;
+    for (int w = 0; w <= n_wg; ++w) {
+        const double target = pre[n] * double(w) / double(n_wg);
+        while (i < n && pre[i] < target) ++i;
+        p->wg_begin[size_t(w)] = int32_t(i);
+    }
+    p->wg_begin[size_t(n_wg)] = int32_t(n);
+}
+
+vbw::Storage storage_of(int32_t dtype) {
+    return dtype == VBW_CF16 ? vbw::Storage::F16 : dtype == VBW_CBF16 ? vbw::Storage::BF16 : vbw::Storage::C64;
+}
+
 void free_device(vbw_plan_s *p) {
     if (p->host_only) return;
     int prev = 0;
@@ -215,6 +238,7 @@ void free_device(vbw_plan_s *p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_wg_begin) (void)hipFree(p->d_wg_begin);
     if (p->d_v) (void)hipFree(p->d_v);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_dyn) (void)hipFree(p->d_dyn);
@@ -226,6 +250,7 @@ void free_device(vbw_plan_s *p) {
     p->graph = nullptr;
     p->cap_stream = nullptr;
     p->d_items = nullptr;
+    p->d_wg_begin = nullptr;
     p->d_v = nullptr;
     p->d_tw = nullptr;
     p->d_dyn = nullptr;
@@ -286,6 +311,17 @@ vbw_status setup_device(vbw_plan_s *p) {
     p->d_v = static_cast<float *>(d);
     if ((e = dev_alloc(&d, vbw::kTwiddleN * sizeof(float2))) != hipSuccess) return from_hip(e);
     p->d_tw = static_cast<float2 *>(d);
+    int n_cu = 0;
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess)
+        return from_hip(e);
+    const int per_cu = vbw::ols_fft_wg_per_cu(p->log2n_fixed, storage_of(p->dtype), (p->flags & VBW_F32_OUT) != 0);
+    const int n_wg = int(std::max<size_t>(1, std::min<size_t>(p->items.size(), size_t(n_cu) * size_t(per_cu))));
+    partition_items(p, n_wg);
+    if ((e = dev_alloc(&d, p->wg_begin.size() * sizeof(int32_t))) != hipSuccess) return from_hip(e);
+    p->d_wg_begin = static_cast<int32_t *>(d);
+    if ((e = hipMemcpy(p->d_wg_begin, p->wg_begin.data(), p->wg_begin.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return from_hip(e);
     if ((e = hipEventCreateWithFlags(&p->upload_evt, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
     if ((e = hipEventCreateWithFlags(&p->done_evt, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
     vbw_status st = alloc_dyn(p, std::max<size_t>(p->sched_entries(), 2 * p->ch.size()));
@@ -402,12 +438,9 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
     a.v = p->d_v;
     a.tw = p->d_tw;
     a.n_items = int32_t(p->items.size());
-    a.xcd_remap = 1;
+    a.wg_begin = p->d_wg_begin;
+    a.n_wg = int32_t(p->wg_begin.empty() ? 0 : p->wg_begin.size() - 1);
     return a;
-}
-
-vbw::Storage storage_of(int32_t dtype) {
-    return dtype == VBW_CF16 ? vbw::Storage::F16 : dtype == VBW_CBF16 ? vbw::Storage::BF16 : vbw::Storage::C64;
 }
 
 hipError_t launch(const vbw_plan_s *p, hipStream_t s) {
@@ -538,7 +571,7 @@ int64_t vbw_plan_query(vbw_plan_t p, int32_t q) {
         case VBW_Q_TOTAL_SAMPLES: return p->total_samples;
         case VBW_Q_WORKGROUP: return vbw::kThreads;
         case VBW_Q_LDS_BYTES: return int64_t(vbw::kLdsValues * sizeof(float2));
-        case VBW_Q_GRID: return int64_t(p->items.size());
+        case VBW_Q_GRID: return int64_t(p->wg_begin.empty() ? 0 : p->wg_begin.size() - 1);
         case VBW_Q_KERNEL_VARIANT: return p->variant;
     }
     return VBW_EINVAL;
@@ -550,6 +583,18 @@ int32_t vbw_block_k1(vbw_plan_t p, int32_t channel, int64_t block) {
     for (auto &pr : p->sched[channel].e)
         if (pr.first <= block) k1 = pr.second;
     return k1;
+}
+
+vbw_status vbw_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+    if (bytes < 0 || (bytes > 0 && (!src || !dst))) return VBW_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) return VBW_EINVAL;
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+    if (bytes > 0 && s0 < d0 + uintptr_t(bytes) && d0 < s0 + uintptr_t(bytes)) return VBW_EINVAL;
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = vbw::launch_copy(src, dst, bytes, n_cu, static_cast<hipStream_t>(stream));
+    return from_hip(e);
 }
 
 vbw_status vbw_twiddle_table(int32_t n, float *out) {

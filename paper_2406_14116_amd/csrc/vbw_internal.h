@@ -55,13 +55,21 @@ struct LaunchArgs {
     const float2 *tw;        // w_4096^r, r < 4096
     const void *const *x;    // per-channel input pointers
     void *const *y;          // per-channel output pointers
+    const int32_t *wg_begin; // workgroup w owns items [wg_begin[w], wg_begin[w+1])
     int32_t n_items;
-    int32_t xcd_remap;       // nonzero: keep consecutive items on one XCD
+    int32_t n_wg;            // workgroups in the (persistent) launch
 };
+
+// Resident workgroups per CU of the kernel used for log2n_fixed (0: the
+// kernel that dispatches on N), for sizing the persistent launch.
+int ols_fft_wg_per_cu(int log2n_fixed, Storage in, bool f32_out);
 
 // Host launchers (ols_fft.hip).  log2n_fixed = 0 selects the kernel that
 // dispatches on each item's N; otherwise every item must have that N.
 hipError_t launch_ols_fft(const LaunchArgs &args, int log2n_fixed, Storage in,
                           bool f32_out, hipStream_t stream);
+
+// Streaming copy of `bytes` bytes (copy.hip); src and dst 16-byte aligned.
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int n_cu, hipStream_t stream);
 
 }  // namespace vbw

@@ -13,7 +13,7 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvbw.so")
+LIB_PATH = os.environ.get("VBW_LIBRARY", os.path.join(HERE, "libvbw.so"))
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vbw.h")
 
 VBW_OK, VBW_EINVAL, VBW_ERANGE, VBW_ENOMEM, VBW_EDEVICE, VBW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
@@ -68,6 +68,8 @@ def lib():
         L.vbw_plan_query.restype = ctypes.c_int64
         L.vbw_block_k1.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
         L.vbw_block_k1.restype = ctypes.c_int32
+        L.vbw_copy.argtypes = [P, P, ctypes.c_int64, P]
+        L.vbw_copy.restype = ctypes.c_int
         L.vbw_twiddle_table.argtypes = [ctypes.c_int32, P]
         L.vbw_twiddle_table.restype = ctypes.c_int
         _LIB = L
@@ -91,6 +93,19 @@ def twiddle_table(n: int) -> np.ndarray:
     if rc != VBW_OK:
         raise VbwError(rc, "vbw_twiddle_table")
     return out.reshape(n, 2)
+
+
+def copy(src, dst, stream=None) -> None:
+    """Streaming device copy of src into dst (torch tensors of equal byte size)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy: size mismatch")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib().vbw_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream)
+    if rc != VBW_OK:
+        raise VbwError(rc, "vbw_copy")
 
 
 class Plan:

@@ -139,6 +139,12 @@ def test_edge_shapes_every_n(mixed):
                 continue
             assert np.all(np.isfinite(y)), spec
             e = ols.error_db(y, ref)
+            if spec[4] < 2 * spec[1] or spec[4] < (spec[0] - spec[1]) // 2 + spec[1]:
+                # a channel that ends before the filter's delay D (plus a block)
+                # is all start-up transient: its output can hold almost no
+                # energy while float32 rounding scales with the input, so it is
+                # judged against the input energy
+                e = 10 * np.log10(np.sum(np.abs(y - ref) ** 2) / np.sum(np.abs(x) ** 2) + 1e-300)
             worst = max(worst, e)
             assert e <= FP32_DB, (spec, e)
     say("worst dB", worst)
