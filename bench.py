@@ -121,6 +121,31 @@ def accuracy(w, ys, oracle_sample, n_channels: int = 4):
     return dbs
 
 
+def copy_bandwidth(nbytes: int, steps: int = 10):
+    """GB/s of a plain device copy of nbytes (library copy kernel and torch's
+    copy), counting read + write bytes like the filter's algorithmic bytes."""
+    import torch
+    from paper_2406_14116_amd import vbw
+    n = nbytes // 8
+    x = torch.empty(n, dtype=torch.complex64, device="cuda").normal_()
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn in (("vbw_copy", lambda: vbw.copy(x, y)), ("torch_copy", lambda: y.copy_(x))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = 2 * n * 8 / (a.elapsed_time(b) / steps * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +155,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the library's plain copy over the workload's byte count "
+                         "(reference for the memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -142,6 +170,16 @@ def main():
 
     w, dtype = make_workload(args.config)
     log(f"bench: {w.name}: {len(w.channels)} channels, {w.total_samples()} samples, storage {dtype}")
+    if args.copy_calibration:
+        nbytes = w.total_samples() * (8 if dtype == "c64" else 4)
+        x = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda").normal_()
+        y = torch.empty_like(x)
+        for _ in range(args.warmup + args.steps):
+            vbw.copy(x, y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": nbytes,
+                          "launches": args.warmup + args.steps}), flush=True)
+        return
     t0 = time.perf_counter()
     xs = harness.upload_inputs(w, dtype)
     ys = harness.alloc_outputs(w, dtype)
@@ -173,6 +211,9 @@ def main():
     key = {2: "fp32_64ch_n1024", 3: "batched_512ch", 4: "f16_256ch_n256", 5: "narrow_256ch_n4096"}[args.config]
     traffic = traffic_from_profile(key)
 
+    copy = copy_bandwidth(total * bytes_per_sample // 2)
+    log(f"bench: plain copy of the same bytes: {copy}")
+
     cpu = None
     sample = None
     if not args.no_cpu_baseline:
@@ -200,7 +241,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_ms": kernel_ms,
-                     "algorithmic_bytes": total * bytes_per_sample},
+                     "algorithmic_bytes": total * bytes_per_sample,
+                     "copy_gbs": copy, "frac_of_copy": achieved / max(copy.values())},
         "cpu_baseline": cpu,
         "accuracy_db": {"max": max(dbs) if dbs else None,
                         "median": float(np.median(dbs)) if dbs else None,
