@@ -74,7 +74,7 @@ typedef enum vbw_engine {
 #define VBW_GRAPH      (1u << 1)  /* replay a captured HIP graph in steady state */
 #define VBW_F32_OUT    (1u << 2)  /* write float32 output for 16-bit input */
 #define VBW_HOST_ONLY  (1u << 3)  /* validate and build host tables only; no device use */
-#define VBW_AUTOTUNE   (1u << 4)  /* time the launch variants once at plan time */
+#define VBW_AUTOTUNE   (1u << 4)  /* time the launch variants on the first vbw_filter */
 
 /* One channel.  `reserved` must be 0. */
 typedef struct vbw_channel {
@@ -133,6 +133,10 @@ vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
  * hipStream_t (NULL: the null stream).  Asynchronous: no host
  * synchronisation except when pointer or schedule tables must be re-uploaded
  * while an earlier upload is still in flight.
+ * With VBW_AUTOTUNE the first call also times every launch variant on these
+ * buffers (blocking; the outputs are the filter's outputs all the same) and
+ * keeps the fastest for the plan's lifetime.  With VBW_GRAPH and a non-null
+ * stream the launches are captured once into a HIP graph and replayed.
  * Errors: VBW_EINVAL (NULL plan or arrays, NULL pointer for a channel with
  * len > 0, an output range overlapping any other input or output range);
  * VBW_EUNSUPPORTED for a VBW_HOST_ONLY plan; VBW_EDEVICE from HIP. */
@@ -154,8 +158,9 @@ typedef enum vbw_query {
     VBW_Q_TOTAL_SAMPLES = 3,   /* sum over channels of len */
     VBW_Q_WORKGROUP = 4,       /* threads per workgroup */
     VBW_Q_LDS_BYTES = 5,       /* LDS per workgroup */
-    VBW_Q_GRID = 6,            /* workgroups per launch */
-    VBW_Q_KERNEL_VARIANT = 7   /* index of the chosen launch variant */
+    VBW_Q_GRID = 6,            /* workgroups over the launches of one call */
+    VBW_Q_KERNEL_VARIANT = 7,  /* index of the chosen launch variant */
+    VBW_Q_N_VARIANTS = 8       /* launch variants the autotuner chooses from */
 } vbw_query;
 
 /* Value of `q` for the plan, or a negative vbw_status. */

@@ -25,6 +25,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "vbw_internal.h"
 
 #ifndef VBW_PREFETCH
@@ -172,7 +174,14 @@ template <int R, bool INV> __device__ __forceinline__ void dft_small(float2 (&a)
 // num_records reads 0 and drops stores) provides the zero fill past the end
 // of the input and the truncation of the last output block.
 constexpr int kBufFlags = 0x00020000;   // raw buffer, 32-bit dword format
-constexpr int kNT = 2;                  // non-temporal cache policy: streamed once
+#ifndef VBW_LOAD_POLICY
+#define VBW_LOAD_POLICY 2
+#endif
+#ifndef VBW_STORE_POLICY
+#define VBW_STORE_POLICY 2
+#endif
+constexpr int kLoadPolicy = VBW_LOAD_POLICY;    // cache policy bits of channel-data loads
+constexpr int kStorePolicy = VBW_STORE_POLICY;  // and stores (2: non-temporal, streamed once)
 typedef unsigned u2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int64_t bytes) {
@@ -186,7 +195,7 @@ template <Storage S> struct Io;
 template <> struct Io<Storage::C64> {
     static constexpr int kBytes = 8;
     __device__ static float2 ld(__amdgpu_buffer_rsrc_t r, int off) {
-        const u2v u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kNT);
+        const u2v u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kLoadPolicy);
         return make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
     }
 };
@@ -200,7 +209,7 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
 template <> struct Io<Storage::F16> {
     static constexpr int kBytes = 4;
     __device__ static float2 ld(__amdgpu_buffer_rsrc_t r, int off) {
-        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kNT);
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kLoadPolicy);
         return __half22float2(__builtin_bit_cast(__half2, u));
     }
 };
@@ -208,7 +217,7 @@ template <> struct Io<Storage::F16> {
 template <> struct Io<Storage::BF16> {
     static constexpr int kBytes = 4;
     __device__ static float2 ld(__amdgpu_buffer_rsrc_t r, int off) {
-        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kNT);
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kLoadPolicy);
         return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
     }
 };
@@ -217,12 +226,12 @@ template <Storage S, bool F32OUT> struct Out {
     static constexpr int kBytes = (S == Storage::C64 || F32OUT) ? 8 : 4;
     __device__ static void st(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
         if constexpr (kBytes == 8) {
-            __builtin_amdgcn_raw_buffer_store_b64(u2v{__float_as_uint(v.x), __float_as_uint(v.y)}, r, off, 0, kNT);
+            __builtin_amdgcn_raw_buffer_store_b64(u2v{__float_as_uint(v.x), __float_as_uint(v.y)}, r, off, 0, kStorePolicy);
         } else if constexpr (S == Storage::F16) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __float22half2_rn(v)), r, off, 0, kNT);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __float22half2_rn(v)), r, off, 0, kStorePolicy);
         } else {
             __builtin_amdgcn_raw_buffer_store_b32(f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16), r, off, 0,
-                                                  kNT);
+                                                  kStorePolicy);
         }
     }
 };
@@ -361,6 +370,57 @@ __device__ __forceinline__ void last_pass(float2 (&a)[16], const TwReg<LOG2N> &t
     }
 }
 
+// Stopband-pruned last pass.  Its butterfly b produces bins b + (N/R) s; when
+// the passband and transition band end below N/R (k2 < N/R), every bin with
+// 0 < s < R-1 is stopband, so only s = 0 and s = R-1 can be nonzero
+// (eq. (6): H_R = 0 on k_s).  Forward: compute just those two outputs and zero
+// the rest.  Inverse: the first pass reads just those two inputs.
+template <int R, int S_, bool INV>
+__device__ __forceinline__ float2 wr_mul(float2 a) {   // a * w_R^{S_} (conjugate for INV)
+    return w16mul<INV, ((16 / R) * S_) & 15>(a);
+}
+
+template <int LOG2N, bool INV>
+__device__ __forceinline__ void last_pass_pruned(float2 (&a)[16], const TwReg<LOG2N> &tw) {
+    using Sh = Shape<LOG2N>;
+    constexpr int R = Sh::RLAST;
+    constexpr int U = 16 / R;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float2 c[R];
+        if constexpr (!INV) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) c[r] = a[u + U * r];
+            if constexpr (Sh::NP > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) c[r] = cmul(c[r], tw.last[u * (R - 1) + r - 1]);
+            }
+            // out_0 = sum_r c_r, out_{R-1} = sum_r c_r w_R^{-r}
+            float2 s0 = c[0], s1 = c[0];
+            [&]<int... r>(std::integer_sequence<int, r...>) {
+                ((s0 = cadd(s0, c[r + 1]), s1 = cadd(s1, wr_mul<R, R - (r + 1), false>(c[r + 1]))), ...);
+            }(std::make_integer_sequence<int, R - 1>{});
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[u + U * r] = make_float2(0.f, 0.f);
+            a[u] = s0;
+            a[u + U * (R - 1)] = s1;
+        } else {
+            // c_r = Y_0 + Y_{R-1} w_R^{r}  (inverse DFT of the two nonzero inputs)
+            const float2 y0 = a[u], y1 = a[u + U * (R - 1)];
+            c[0] = cadd(y0, y1);
+            [&]<int... r>(std::integer_sequence<int, r...>) {
+                ((c[r + 1] = cadd(y0, wr_mul<R, r + 1, false>(y1))), ...);
+            }(std::make_integer_sequence<int, R - 1>{});
+            if constexpr (Sh::NP > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) c[r] = cmulc(c[r], tw.last[u * (R - 1) + r - 1]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[u + U * r] = c[r];
+        }
+    }
+}
+
 // Step 3: Y(k) = H_R(k) X(k) / N (eq. (6), mirror H_R(N-k) = H_R(k)).  Slot v
 // holds bin k = t + T v; its mirrored index kk = min(k, N-k) is t + T v for
 // v < 8 and N - T v - t for v >= 8.  When every lane of the wave uses the same
@@ -490,9 +550,7 @@ __device__ __forceinline__ void filter_item(float2 (&a)[16], const LaunchArgs &A
     }
 
     // step 2: forward DFT
-    if constexpr (Sh::NP == 1) {
-        last_pass<LOG2N, false>(a, tw);
-    } else {
+    if constexpr (Sh::NP > 1) {
         dft16<false>(a);                                  // pass 1, Ns = 1
 #pragma unroll
         for (int s = 0; s < 16; ++s) L[17 * t + s] = a[s];
@@ -500,14 +558,20 @@ __device__ __forceinline__ void filter_item(float2 (&a)[16], const LaunchArgs &A
         if constexpr (Sh::NP == 3) mid_pass<LOG2N, false>(a, L, t, tw);
 #pragma unroll
         for (int v = 0; v < 16; ++v) a[v] = L[lds_stride_pos<T>(t, v)];
-        last_pass<LOG2N, false>(a, tw);
     }
+    // every team of the wave must meet the pruning condition (wave-uniform)
+    constexpr int R = Sh::RLAST;
+    const bool prune = (R > 2) && A.prune && __all(k1 + cd.lv - 1 < N / R);
+    if (prune) last_pass_pruned<LOG2N, false>(a, tw);
+    else last_pass<LOG2N, false>(a, tw);
 
     // step 3: H_R and 1/N
     hfso_multiply<LOG2N>(a, t, k1, cd.lv, vlds);
 
-    // step 4: inverse DFT (adjoint passes)
-    last_pass<LOG2N, true>(a, tw);
+    // step 4: inverse DFT (adjoint passes); the first one reads only the
+    // bins that can be nonzero when pruned
+    if (prune) last_pass_pruned<LOG2N, true>(a, tw);
+    else last_pass<LOG2N, true>(a, tw);
     if constexpr (Sh::NP > 1) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) L[lds_stride_pos<T>(t, v)] = a[v];

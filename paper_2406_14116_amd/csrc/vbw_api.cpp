@@ -119,7 +119,17 @@ struct vbw_plan_s {
     int device = 0;
     WorkItem *d_items = nullptr;
     int32_t *d_wg_begin = nullptr;
-    std::vector<int32_t> wg_begin;   // persistent launch: items of workgroup w
+    std::vector<int32_t> wg_begin;   // concatenated per-launch workgroup item ranges
+    // Launch variants: each is a list of persistent launches (one per N group,
+    // or one launch of the kernel that dispatches on N), each with its own
+    // workgroup count and item partition.
+    struct LaunchGroup {
+        int log2n;       // 0: kernel that dispatches on N
+        int wg_off;      // offset of this launch's range table in wg_begin
+        int n_wg;
+    };
+    std::vector<std::vector<LaunchGroup>> variants;
+    bool tuned = false;
     float *d_v = nullptr;
     float2 *d_tw = nullptr;
     unsigned char *d_dyn = nullptr;   // ChannelDev[nch] | x[nch] | y[nch] | SchedDev[cap]
@@ -204,27 +214,82 @@ void build_items(vbw_plan_s *p) {
         }
     }
     p->log2n_fixed = (uniform && first_log2 > 0) ? first_log2 : 0;
+    // group items of equal N (each group is then one contiguous range)
+    std::stable_sort(p->items.begin(), p->items.end(),
+                     [](const WorkItem &a, const WorkItem &b) { return a.log2n < b.log2n; });
 }
 
-// Split the item list into n_wg contiguous ranges of equal estimated cost.
-// A workgroup always works through a whole 4096-value tile, so an item costs
+// Split items [b, e) into n_wg contiguous ranges of equal estimated cost and
+// append the n_wg + 1 range boundaries to wg_begin; returns their offset.  A
+// workgroup always works through a whole 4096-value tile, so an item costs
 // about log2(N) FFT passes plus a fixed part for loads, multiply and stores.
-void partition_items(vbw_plan_s *p, int n_wg) {
-    const size_t n = p->items.size();
+int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg) {
+    const size_t n = e - b;
     std::vector<double> pre(n + 1, 0.0);
-    for (size_t i = 0; i < n; ++i) pre[i + 1] = pre[i] + (p->items[i].log2n + 2.0);
-    p->wg_begin.assign(size_t(n_wg) + 1, 0);
+    for (size_t i = 0; i < n; ++i) pre[i + 1] = pre[i] + (p->items[b + i].log2n + 2.0);
+    const int off = int(p->wg_begin.size());
     size_t i = 0;
     for (int w = 0; w <= n_wg; ++w) {
         const double target = pre[n] * double(w) / double(n_wg);
         while (i < n && pre[i] < target) ++i;
-        p->wg_begin[size_t(w)] = int32_t(i);
+        p->wg_begin.push_back(int32_t(b + (w == n_wg ? n : i)));
     }
-    p->wg_begin[size_t(n_wg)] = int32_t(n);
+    return off;
 }
 
 vbw::Storage storage_of(int32_t dtype) {
     return dtype == VBW_CF16 ? vbw::Storage::F16 : dtype == VBW_CBF16 ? vbw::Storage::BF16 : vbw::Storage::C64;
+}
+
+// Candidate launch shapes (the autotuner times them; variant 0 is the default):
+//   per-N launches at the full resident occupancy, and with one workgroup per
+//   CU fewer; for plans that mix N, also one launch of the kernel that
+//   dispatches on N, at both occupancies.
+void build_variants(vbw_plan_s *p, int n_cu) {
+    p->variants.clear();
+    p->wg_begin.clear();
+    const vbw::Storage st = storage_of(p->dtype);
+    const bool f32 = (p->flags & VBW_F32_OUT) != 0;
+    // contiguous groups of equal N
+    std::vector<std::pair<size_t, size_t>> groups;
+    for (size_t i = 0; i < p->items.size();) {
+        size_t j = i;
+        while (j < p->items.size() && p->items[j].log2n == p->items[i].log2n) ++j;
+        groups.push_back({i, j});
+        i = j;
+    }
+    if (groups.empty()) {
+        p->variants.push_back({});
+        return;
+    }
+    auto make = [&](bool generic, int occupancy_drop) {
+        std::vector<vbw_plan_s::LaunchGroup> v;
+        if (generic) {
+            const int per = std::max(1, vbw::ols_fft_wg_per_cu(0, st, f32) - occupancy_drop);
+            const int n_wg = int(std::max<size_t>(1, std::min<size_t>(p->items.size(), size_t(n_cu) * per)));
+            v.push_back({0, partition_items(p, 0, p->items.size(), n_wg), n_wg});
+            return v;
+        }
+        // split the CUs between N groups in proportion to their cost so the
+        // launches finish together when they overlap
+        double total = 0;
+        for (auto &g : groups)
+            for (size_t i = g.first; i < g.second; ++i) total += p->items[i].log2n + 2.0;
+        for (auto &g : groups) {
+            const int lg = p->items[g.first].log2n;
+            const int per = std::max(1, vbw::ols_fft_wg_per_cu(lg, st, f32) - occupancy_drop);
+            const int n_wg = int(std::max<size_t>(1, std::min<size_t>(g.second - g.first, size_t(n_cu) * per)));
+            v.push_back({lg, partition_items(p, g.first, g.second, n_wg), n_wg});
+        }
+        return v;
+    };
+    p->variants.push_back(make(false, 0));
+    p->variants.push_back(make(false, 1));
+    if (groups.size() > 1) {
+        p->variants.push_back(make(true, 0));
+        p->variants.push_back(make(true, 1));
+    }
+    p->variant = 0;
 }
 
 void free_device(vbw_plan_s *p) {
@@ -314,12 +379,12 @@ vbw_status setup_device(vbw_plan_s *p) {
     int n_cu = 0;
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess)
         return from_hip(e);
-    const int per_cu = vbw::ols_fft_wg_per_cu(p->log2n_fixed, storage_of(p->dtype), (p->flags & VBW_F32_OUT) != 0);
-    const int n_wg = int(std::max<size_t>(1, std::min<size_t>(p->items.size(), size_t(n_cu) * size_t(per_cu))));
-    partition_items(p, n_wg);
-    if ((e = dev_alloc(&d, p->wg_begin.size() * sizeof(int32_t))) != hipSuccess) return from_hip(e);
+    build_variants(p, n_cu);
+    if ((e = dev_alloc(&d, std::max<size_t>(1, p->wg_begin.size()) * sizeof(int32_t))) != hipSuccess)
+        return from_hip(e);
     p->d_wg_begin = static_cast<int32_t *>(d);
-    if ((e = hipMemcpy(p->d_wg_begin, p->wg_begin.data(), p->wg_begin.size() * sizeof(int32_t),
+    if (!p->wg_begin.empty() &&
+        (e = hipMemcpy(p->d_wg_begin, p->wg_begin.data(), p->wg_begin.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return from_hip(e);
     if ((e = hipEventCreateWithFlags(&p->upload_evt, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
@@ -439,13 +504,54 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
     a.tw = p->d_tw;
     a.n_items = int32_t(p->items.size());
     a.wg_begin = p->d_wg_begin;
-    a.n_wg = int32_t(p->wg_begin.empty() ? 0 : p->wg_begin.size() - 1);
+    a.n_wg = 0;
+    a.prune = (p->flags & VBW_NO_PRUNE) ? 0 : 1;
+    a.pad = 0;
     return a;
 }
 
-hipError_t launch(const vbw_plan_s *p, hipStream_t s) {
-    return vbw::launch_ols_fft(launch_args(p), p->log2n_fixed, storage_of(p->dtype),
-                               (p->flags & VBW_F32_OUT) != 0, s);
+hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant) {
+    vbw::LaunchArgs a = launch_args(p);
+    for (const auto &g : p->variants[size_t(variant)]) {
+        a.wg_begin = p->d_wg_begin + g.wg_off;
+        a.n_wg = g.n_wg;
+        hipError_t e = vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), (p->flags & VBW_F32_OUT) != 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Time every launch variant on the caller's buffers (filtering is idempotent:
+// each run rewrites the same outputs) and keep the fastest.  Blocking, once.
+vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
+    if (p->variants.size() < 2) {
+        p->tuned = true;
+        return VBW_OK;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    float best = 0.f;
+    int best_v = 0;
+    for (size_t v = 0; e == hipSuccess && v < p->variants.size(); ++v) {
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch(p, s, int(v));
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(p, s, int(v));
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && (v == 0 || ms < best)) {
+            best = ms;
+            best_v = int(v);
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return from_hip(e);
+    p->variant = best_v;
+    p->tuned = true;
+    return VBW_OK;
 }
 
 }  // namespace
@@ -522,12 +628,13 @@ vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *
                            std::equal(y, y + nch, p->last_y.begin());
     if (!ptrs_same || p->sched_dirty) st = upload_dyn(p, x, y, s);
 
+    if (st == VBW_OK && !p->items.empty() && (p->flags & VBW_AUTOTUNE) && !p->tuned) st = autotune(p, s);
     if (st == VBW_OK && !p->items.empty()) {
         if ((p->flags & VBW_GRAPH) && s != nullptr) {
             if (!p->graph_exec) {
                 e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    hipError_t le = launch(p, p->cap_stream);
+                    hipError_t le = launch(p, p->cap_stream, p->variant);
                     e = hipStreamEndCapture(p->cap_stream, &p->graph);
                     if (le != hipSuccess) e = le;
                 }
@@ -536,7 +643,7 @@ vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *
             }
             if (st == VBW_OK) st = from_hip(hipGraphLaunch(p->graph_exec, s));
         } else {
-            st = from_hip(launch(p, s));
+            st = from_hip(launch(p, s, p->variant));
         }
     }
     if (st == VBW_OK) st = from_hip(hipEventRecord(p->done_evt, s));
@@ -571,7 +678,13 @@ int64_t vbw_plan_query(vbw_plan_t p, int32_t q) {
         case VBW_Q_TOTAL_SAMPLES: return p->total_samples;
         case VBW_Q_WORKGROUP: return vbw::kThreads;
         case VBW_Q_LDS_BYTES: return int64_t(vbw::kLdsValues * sizeof(float2));
-        case VBW_Q_GRID: return int64_t(p->wg_begin.empty() ? 0 : p->wg_begin.size() - 1);
+        case VBW_Q_GRID: {
+            int64_t g = 0;
+            if (!p->variants.empty())
+                for (auto &lg : p->variants[size_t(p->variant)]) g += lg.n_wg;
+            return g;
+        }
+        case VBW_Q_N_VARIANTS: return int64_t(p->variants.size());
         case VBW_Q_KERNEL_VARIANT: return p->variant;
     }
     return VBW_EINVAL;

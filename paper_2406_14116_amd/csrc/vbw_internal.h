@@ -58,6 +58,8 @@ struct LaunchArgs {
     const int32_t *wg_begin; // workgroup w owns items [wg_begin[w], wg_begin[w+1])
     int32_t n_items;
     int32_t n_wg;            // workgroups in the (persistent) launch
+    int32_t prune;           // nonzero: stopband-pruned last forward / first inverse pass
+    int32_t pad;
 };
 
 // Resident workgroups per CU of the kernel used for log2n_fixed (0: the

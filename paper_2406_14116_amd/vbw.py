@@ -20,7 +20,8 @@ VBW_OK, VBW_EINVAL, VBW_ERANGE, VBW_ENOMEM, VBW_EDEVICE, VBW_EUNSUPPORTED = 0, -
 DTYPES = {"c64": 0, "f16": 1, "bf16": 2}
 ENGINES = {"fft": 0, "gemm": 1}
 NO_PRUNE, GRAPH, F32_OUT, HOST_ONLY, AUTOTUNE = 1, 2, 4, 8, 16
-Q_N_CHANNELS, Q_N_ITEMS, Q_TOTAL_BLOCKS, Q_TOTAL_SAMPLES, Q_WORKGROUP, Q_LDS_BYTES, Q_GRID, Q_VARIANT = range(8)
+(Q_N_CHANNELS, Q_N_ITEMS, Q_TOTAL_BLOCKS, Q_TOTAL_SAMPLES, Q_WORKGROUP, Q_LDS_BYTES, Q_GRID, Q_VARIANT,
+ Q_N_VARIANTS) = range(9)
 
 
 class vbw_channel(ctypes.Structure):

@@ -225,6 +225,32 @@ def test_graph_replay_matches_eager():
     pg.close()
 
 
+def test_autotuned_variants_agree():
+    """Every launch variant (per-N launches, one launch dispatching on N, two
+    occupancies) computes the same thing; the autotuner keeps one of them."""
+    rng = np.random.default_rng(6)
+    specs = [(256, 192, 8, 20, 90000, (256, 8)), (1024, 768, 16, 100, 300000, (1024, 16)),
+             (2048, 1536, 16, 300, 200000, (2048, 16)), (512, 384, 8, 50, 50000, (512, 8))]
+    v_sets = v_for({s[5] for s in specs})
+    chans, pool = channels_from(specs, v_sets)
+    xs = [torch.from_numpy(crandn(rng, s[4])).cuda() for s in specs]
+    ref = [ols.channel_hfso(x.cpu().numpy().astype(np.complex128), s[0], s[1], v_sets[s[5]], [(0, s[3])])
+           for x, s in zip(xs, specs)]
+    p = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE)
+    assert p.query(vbw.Q_N_VARIANTS) == 4
+    ys = [torch.empty_like(x) for x in xs]
+    run_plan(p, xs, ys)
+    chosen = p.query(vbw.Q_VARIANT)
+    say("autotune chose variant", chosen, "grid", p.query(vbw.Q_GRID))
+    assert 0 <= chosen < 4
+    for y, r in zip(ys, ref):
+        assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
+    run_plan(p, xs, ys)                      # tuned plan, second call
+    for y, r in zip(ys, ref):
+        assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
+    p.close()
+
+
 def test_filter_rejects_overlap_and_null():
     specs = [(256, 192, 8, 20, 10000, (256, 8))]
     chans, pool = channels_from(specs, v_for({(256, 8)}))
