@@ -66,7 +66,8 @@ typedef enum vbw_dtype {
 
 typedef enum vbw_engine {
     VBW_ENGINE_FFT = 0,     /* LDS-staged Stockham FFT, float32 */
-    VBW_ENGINE_GEMM = 1     /* small DFTs as MFMA GEMMs (16-bit storage only) */
+    VBW_ENGINE_GEMM = 1     /* N = 256 as 16 x 16 MFMA products, FP16 hi/lo split
+                               operands, FP32 accumulation (16-bit storage only) */
 } vbw_engine;
 
 /* Plan flags. */
@@ -111,7 +112,8 @@ typedef struct vbw_plan_s *vbw_plan_t;
  * len, a non-finite V, an unknown dtype/engine/flag or nonzero reserved
  * field; VBW_ERANGE when k1 < 1 or k2 = k1 + L_V - 1 > N/2 - 1 (the one
  * exception is the all-pass L_V = 0, k1 = N/2 + 1); VBW_EUNSUPPORTED for the
- * GEMM engine with float32 storage; VBW_ENOMEM / VBW_EDEVICE from HIP.
+ * GEMM engine with float32 storage or any channel with N != 256;
+ * VBW_ENOMEM / VBW_EDEVICE from HIP.
  * On error *out is set to NULL. */
 vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out);
 

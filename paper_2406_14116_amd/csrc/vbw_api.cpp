@@ -181,7 +181,12 @@ vbw_status validate_desc(const vbw_plan_desc *d) {
         if (!k1_in_range(ch.n, ch.lv, ch.k1)) range = VBW_ERANGE;
     }
     if (range != VBW_OK) return range;
-    if (d->engine == VBW_ENGINE_GEMM) return VBW_EUNSUPPORTED;
+    if (d->engine == VBW_ENGINE_GEMM) {
+        // matrix-core engine: 16-bit storage and N = 256 only
+        if (d->dtype == VBW_C64) return VBW_EUNSUPPORTED;
+        for (int32_t c = 0; c < d->n_channels; ++c)
+            if (d->channels[c].n != 256) return VBW_EUNSUPPORTED;
+    }
     return VBW_OK;
 }
 
@@ -260,6 +265,15 @@ void build_variants(vbw_plan_s *p, int n_cu) {
     }
     if (groups.empty()) {
         p->variants.push_back({});
+        return;
+    }
+    if (p->engine == VBW_ENGINE_GEMM) {
+        for (int drop = 0; drop < 2; ++drop) {
+            const int per = std::max(1, vbw::ols_gemm_wg_per_cu(st, f32) - drop);
+            const int n_wg = int(std::max<size_t>(1, std::min<size_t>(p->items.size(), size_t(n_cu) * per)));
+            p->variants.push_back({{-1, partition_items(p, 0, p->items.size(), n_wg), n_wg}});
+        }
+        p->variant = 0;
         return;
     }
     auto make = [&](bool generic, int occupancy_drop) {
@@ -515,7 +529,9 @@ hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant) {
     for (const auto &g : p->variants[size_t(variant)]) {
         a.wg_begin = p->d_wg_begin + g.wg_off;
         a.n_wg = g.n_wg;
-        hipError_t e = vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), (p->flags & VBW_F32_OUT) != 0, s);
+        const bool f32 = (p->flags & VBW_F32_OUT) != 0;
+        hipError_t e = g.log2n < 0 ? vbw::launch_ols_gemm(a, storage_of(p->dtype), f32, s)
+                                   : vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), f32, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -71,6 +71,10 @@ int ols_fft_wg_per_cu(int log2n_fixed, Storage in, bool f32_out);
 hipError_t launch_ols_fft(const LaunchArgs &args, int log2n_fixed, Storage in,
                           bool f32_out, hipStream_t stream);
 
+// Matrix-core engine (ols_gemm.hip): N = 256, 16-bit storage only.
+int ols_gemm_wg_per_cu(Storage in, bool f32_out);
+hipError_t launch_ols_gemm(const LaunchArgs &args, Storage in, bool f32_out, hipStream_t stream);
+
 // Streaming copy of `bytes` bytes (copy.hip); src and dst 16-byte aligned.
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int n_cu, hipStream_t stream);
 

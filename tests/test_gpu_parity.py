@@ -18,6 +18,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FP32_DB = -110.0
+GEMM_COMPUTE_DB = -120.0
 
 
 def say(*a):
@@ -355,8 +356,9 @@ def test_config5_full_size_sampled():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("engine", ["fft", "gemm"])
 @pytest.mark.parametrize("storage,bound", [("f16", -65.0), ("bf16", -50.0)])
-def test_config4_storage_variants(storage, bound):
+def test_config4_storage_variants(storage, bound, engine):
     """16-bit storage, float32 arithmetic.  End to end against the oracle on
     the unquantized input (input and output rounding included), and compute
     only (oracle on the stored 16-bit input, float32 output) at -110 dB."""
@@ -364,15 +366,17 @@ def test_config4_storage_variants(storage, bound):
     xs_c128 = [wl.channel_samples(w, c) for c in range(len(w.channels))]
     xs = [harness.host_to_storage(x, storage).cuda() for x in xs_c128]
     ys = harness.alloc_outputs(w, storage)
-    plan = vbw.Plan.from_workload(w)
+    plan = vbw.Plan.from_workload(w, engine=engine)
     run_plan(plan, xs, ys)
     dbs = check_sampled(w, ys, lambda ci: xs_c128[ci], tol=bound, channels=range(0, 32, 4), n_random=4)
-    say(storage, "end-to-end dB max/median", max(dbs), float(np.median(dbs)))
+    say(storage, engine, "end-to-end dB max/median", max(dbs), float(np.median(dbs)))
     plan.close()
     ys32 = harness.alloc_outputs(w, storage, f32_out=True)
-    p32 = vbw.Plan.from_workload(w, flags=vbw.F32_OUT)
+    p32 = vbw.Plan.from_workload(w, engine=engine, flags=vbw.F32_OUT)
     run_plan(p32, xs, ys32)
+    # compute-only: float32 FFT engine -110 dB; matrix-core engine with FP16
+    # hi/lo operands (about 22 significant bits per operand) -120 dB
     dbs = check_sampled(w, ys32, lambda ci: harness.storage_to_c128(xs[ci]), channels=range(0, 32, 4),
-                        n_random=4)
-    say(storage, "compute-only dB max/median", max(dbs), float(np.median(dbs)))
+                        n_random=4, tol=FP32_DB if engine == "fft" else GEMM_COMPUTE_DB)
+    say(storage, engine, "compute-only dB max/median", max(dbs), float(np.median(dbs)))
     p32.close()
