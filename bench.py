@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "complex output samples/s at ≤ −110 dB vs FP64 oracle; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2406_14116_amd", "csrc", "ols_fft.hip")
+CSRC = os.path.join(ROOT, "paper_2406_14116_amd", "csrc")
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -37,25 +37,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(engine: str) -> str:
+    src = os.path.join(CSRC, "ols_gemm.hip" if engine == "gemm" else "ols_fft.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(workload_key: str):
+def traffic_from_profile(kernel: str, workload_key: str, engine: str):
     """HBM bytes per launch measured by rocprofv3 counters, if the committed
     summary was taken on the current kernel source."""
-    path = os.path.join(PROFILE_DIR, f"ols_fft_{workload_key}_pmc.md")
+    path = os.path.join(PROFILE_DIR, f"{kernel}_{workload_key}_pmc.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != kernel_hash():
+    if not m or not t or m.group(1) != kernel_hash(engine):
         return None
     return float(t.group(1))
 
 
-def make_workload(cfg: int):
+def make_workload(cfg: int, storage: str):
     from paper_2406_14116_amd import workloads as wl
     if cfg == 2:
         return wl.config2(), "c64"
@@ -64,17 +65,31 @@ def make_workload(cfg: int):
     if cfg == 5:
         return wl.config5(), "c64"
     if cfg == 4:
-        return wl.config4(storage="f16"), "f16"
-    raise SystemExit(f"config {cfg} is not a bench workload")
+        return wl.config4(storage=storage), storage
+    raise SystemExit(f"config {cfg} is not a bench workload (2, 3, 4, 5)")
 
 
-def cpu_baseline(w, budget_s: float):
+def workload_key(cfg: int, storage: str, engine: str) -> str:
+    return {2: "fp32_64ch_n1024", 3: "batched_512ch_mixed", 5: "narrow_256ch_n4096",
+            4: f"{storage}_256ch_n256"}[cfg] + ("_gemm" if engine == "gemm" else "")
+
+
+def oracle_input(w, ci: int, dtype: str):
+    """What the oracle filters: the values the GPU reads for float32 storage
+    (exact in float64), the unquantized samples for 16-bit storage (so the
+    error is end to end, input and output rounding included)."""
+    from paper_2406_14116_amd import workloads as wl
+    if dtype == "c64":
+        return wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128)
+    return wl.channel_samples(w, ci)
+
+
+def cpu_baseline(w, dtype: str, budget_s: float):
     """Time the FP64 oracle on a bounded sample: seeded random blocks of
     channel 0, as many as fit the time budget at the calibrated rate."""
     from oracle import ols
-    from paper_2406_14116_amd import workloads as wl
     c = w.channels[0]
-    x = wl.channel_samples(w, 0, dtype=np.complex64).astype(np.complex128)
+    x = oracle_input(w, 0, dtype)
     v = w.v_sets[c.v_key]
     threads = ols.max_threads()
     rng = np.random.default_rng(77)
@@ -94,11 +109,10 @@ def cpu_baseline(w, budget_s: float):
                       f"OpenMP over blocks"}, (blocks, out)
 
 
-def accuracy(w, ys, oracle_sample, n_channels: int = 4):
+def accuracy(w, dtype, ys, oracle_sample, n_channels: int = 4):
     """dB of the timed output against the oracle on sampled blocks."""
     from oracle import ols
     from paper_2406_14116_amd import harness
-    from paper_2406_14116_amd import workloads as wl
     rng = np.random.default_rng(5)
     dbs = []
     blocks0, ref0 = oracle_sample
@@ -113,7 +127,7 @@ def accuracy(w, ys, oracle_sample, n_channels: int = 4):
         c = w.channels[int(ci)]
         sw = c.schedule[0][0] if c.schedule else None
         blocks = harness.sample_blocks(c.n_blocks(), rng, sw, n_random=2)
-        x = wl.channel_samples(w, int(ci), dtype=np.complex64).astype(np.complex128)
+        x = oracle_input(w, int(ci), dtype)
         ref = ols.blocks_hfso(x, c.n, c.hop, w.v_sets[c.v_key], c.full_schedule(), blocks=blocks)
         g = [harness.storage_to_c128(harness.block_slice(ys[int(ci)], c.hop, b, c.length)) for b in blocks]
         want = [r[: len(gg)] for gg, r in zip(g, ref)]
@@ -155,6 +169,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--engine", choices=("fft", "gemm"), default="fft",
+                    help="gemm: matrix-core DFTs (16-bit storage, N = 256: config 4)")
+    ap.add_argument("--storage", choices=("f16", "bf16"), default="f16", help="config 4 storage")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the library's plain copy over the workload's byte count "
                          "(reference for the memory counters)")
@@ -168,7 +185,7 @@ def main():
     import torch
     from paper_2406_14116_amd import harness, vbw
 
-    w, dtype = make_workload(args.config)
+    w, dtype = make_workload(args.config, args.storage)
     log(f"bench: {w.name}: {len(w.channels)} channels, {w.total_samples()} samples, storage {dtype}")
     if args.copy_calibration:
         nbytes = w.total_samples() * (8 if dtype == "c64" else 4)
@@ -184,7 +201,7 @@ def main():
     xs = harness.upload_inputs(w, dtype)
     ys = harness.alloc_outputs(w, dtype)
     log(f"bench: inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
-    plan = vbw.Plan.from_workload(w, dtype=dtype, flags=args.flags)
+    plan = vbw.Plan.from_workload(w, dtype=dtype, engine=args.engine, flags=args.flags)
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -208,8 +225,9 @@ def main():
     total = w.total_samples()
     bytes_per_sample = 16 if dtype == "c64" else 8
     achieved = total * bytes_per_sample / (kernel_ms * 1e-3) / 1e9
-    key = {2: "fp32_64ch_n1024", 3: "batched_512ch", 4: "f16_256ch_n256", 5: "narrow_256ch_n4096"}[args.config]
-    traffic = traffic_from_profile(key)
+    key = workload_key(args.config, dtype, args.engine)
+    kernel = "ols_gemm" if args.engine == "gemm" else "ols_fft"
+    traffic = traffic_from_profile(kernel, key, args.engine)
 
     copy = copy_bandwidth(total * bytes_per_sample // 2)
     log(f"bench: plain copy of the same bytes: {copy}")
@@ -218,8 +236,8 @@ def main():
     sample = None
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
-        cpu, sample = cpu_baseline(w, args.cpu_budget)
-    dbs = accuracy(w, ys, sample) if sample is not None else []
+        cpu, sample = cpu_baseline(w, dtype, args.cpu_budget)
+    dbs = accuracy(w, dtype, ys, sample) if sample is not None else []
 
     c0 = w.channels[0]
     line = {
@@ -237,7 +255,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "channels": len(w.channels), "total_samples": total,
                    "n": c0.n if args.config != 3 else "mixed", "hop": c0.hop if args.config != 3 else "3N/4",
-                   "storage": dtype, "description": w.description},
+                   "storage": dtype, "engine": args.engine, "variant": plan.query(vbw.Q_VARIANT),
+                   "description": w.description},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_ms": kernel_ms,
@@ -246,7 +265,9 @@ def main():
         "cpu_baseline": cpu,
         "accuracy_db": {"max": max(dbs) if dbs else None,
                         "median": float(np.median(dbs)) if dbs else None,
-                        "channels_checked": len(dbs)},
+                        "channels_checked": len(dbs),
+                        "versus": "oracle on the stored float32 input" if dtype == "c64" else
+                                  "oracle on the unquantized input (end to end: input and output rounding)"},
     }
     plan.close()
     print(json.dumps(line), flush=True)
