@@ -1,9 +1,12 @@
 // ols_fft.hip -- gfx950 kernels for overlap-save variable-bandwidth filtering
 // with HFSO coefficients (Moryakova & Johansson, arXiv 2406.14116).
 //
-// One workgroup (256 threads, 4 waves) owns one 4096-value tile: 4096/N
-// consecutive OLS blocks of one channel.  Each block is handled by a team of
-// N/16 threads and every thread holds 16 complex float32 values in registers.
+// A persistent workgroup (256 threads, 4 waves) holds 4096/N teams of N/16
+// threads; every thread holds 16 complex float32 values in registers and each
+// team filters one OLS block at a time.  The workgroup works through spans
+// (runs of consecutive blocks of one channel); every team takes a contiguous
+// part of the span, so when hop = 3N/4 the N/4 input samples one block shares
+// with the next are carried over instead of read again.
 // Per block (Sec. II, steps 1-4):
 //   1. gather: thread t loads segment samples t + (N/16) v, v < 16 (coalesced
 //      across the team; zero outside [0, len));
@@ -29,9 +32,6 @@
 
 #include "vbw_internal.h"
 
-#ifndef VBW_PREFETCH
-#define VBW_PREFETCH 0
-#endif
 #ifndef VBW_WAVES_PER_EU
 #define VBW_WAVES_PER_EU 3
 #endif
@@ -170,7 +170,7 @@ template <int R, bool INV> __device__ __forceinline__ void dft_small(float2 (&a)
 
 // ------------------------------------------------------------ storage
 // Channel data is read and written through buffer resources: 32-bit byte
-// offsets from a per-item base, and the hardware range check (offset >=
+// offsets from a per-span base, and the hardware range check (offset >=
 // num_records reads 0 and drops stores) provides the zero fill past the end
 // of the input and the truncation of the last output block.
 constexpr int kBufFlags = 0x00020000;   // raw buffer, 32-bit dword format
@@ -483,30 +483,9 @@ template <typename T> __device__ __forceinline__ T ld_uniform(const T *p, int i)
 __device__ __forceinline__ WorkItem load_item(const LaunchArgs &A, int i) { return ld_uniform(A.items, i); }
 __device__ __forceinline__ ChannelDev load_channel(const LaunchArgs &A, int c) { return ld_uniform(A.ch, c); }
 
-// Step 1: gather segment [m hop - (N - hop), m hop + hop) of block
-// m = first_block + team into slots v = t + T v.  One code path for every
-// item: samples before 0 (the zero history of the first blocks) get an
+// Samples before 0 (the zero history of a channel's first blocks) get an
 // offset past the resource's end and read as 0, like samples past len.
 constexpr int kOutOfRange = int(0x80000000u);
-
-template <int LOG2N, Storage S>
-__device__ __forceinline__ void gather(float2 (&a)[16], const LaunchArgs &A, const WorkItem &it,
-                                       const ChannelDev &cd, int team, int t) {
-    using Sh = Shape<LOG2N>;
-    constexpr int N = Sh::N, T = Sh::T;
-    constexpr int EI = Io<S>::kBytes;
-    const int hop = cd.hop;
-    const int64_t base_item = int64_t(it.first_block) * hop - (N - hop);
-    const int64_t clip = base_item > 0 ? base_item : 0;
-    const char *xc = static_cast<const char *>(ld_uniform(A.x, it.channel));
-    const auto xr = make_rsrc(xc + clip * EI, (cd.len - clip) * EI);
-    const int j0 = int(base_item - clip) + team * hop + t;   // index relative to the resource
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int j = j0 + T * v;
-        a[v] = Io<S>::ld(xr, j >= 0 ? j * EI : kOutOfRange);
-    }
-}
 
 constexpr int kVCap = 2048;  // transition values staged in LDS (L_V <= N/2 <= 2048)
 
@@ -515,39 +494,17 @@ struct WgState {
     int lv = -1;
 };
 
-// Steps 2-5 for the blocks of one item, data already gathered into a.
-template <int LOG2N, Storage S, bool F32OUT>
-__device__ __forceinline__ void filter_item(float2 (&a)[16], const LaunchArgs &A, const WorkItem &it,
-                                            const ChannelDev &cd, const TwReg<LOG2N> &tw, float2 *lds,
-                                            float *vlds, WgState &ws) {
+// Steps 2-5 for one block per team, its segment already gathered into a:
+// forward DFT, HFSO multiply, inverse DFT, keep z0(D + j), j < hop.
+template <int LOG2N, Storage S, bool F32OUT, bool CARRY>
+__device__ __forceinline__ void filter_block(float2 (&a)[16], const LaunchArgs &A, const ChannelDev &cd, int k1,
+                                             bool active, __amdgpu_buffer_rsrc_t yr, int o0,
+                                             const TwReg<LOG2N> &tw, float2 *L, const float *vlds, int t) {
     using Sh = Shape<LOG2N>;
     constexpr int N = Sh::N, T = Sh::T;
     constexpr int EO = Out<S, F32OUT>::kBytes;
-    const int tid = threadIdx.x;
-    const int team = tid / T;
-    const int t = tid - team * T;
-    float2 *L = lds + team * lds_pad(N);
     const int hop = cd.hop;
     const int d = (N - hop) >> 1;
-    const int64_t m = int64_t(it.first_block) + team;
-    const bool active = team < it.n_blocks;
-
-    // stage this channel's V in LDS (workgroup-uniform decision)
-    if (cd.v_offset != ws.v_offset || cd.lv != ws.lv) {
-        __syncthreads();
-        for (int i = tid; i < cd.lv; i += kThreads) vlds[i] = A.v[cd.v_offset + i];
-        __syncthreads();
-        ws.v_offset = cd.v_offset;
-        ws.lv = cd.lv;
-    }
-
-    // k1 in force for block m: last schedule entry with from_block <= m
-    // (entries are read with scalar loads; only the comparison is per team)
-    int k1 = ld_uniform(A.sched, cd.sched_begin).k1;
-    for (int e = 1; e < cd.sched_count; ++e) {
-        const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
-        if (sd.from_block <= m) k1 = sd.k1;
-    }
 
     // step 2: forward DFT
     if constexpr (Sh::NP > 1) {
@@ -582,104 +539,155 @@ __device__ __forceinline__ void filter_item(float2 (&a)[16], const LaunchArgs &A
         dft16<true>(a);
     }
 
-    // step 5: keep z0(D + j), j < hop; stores past len are dropped by the
-    // buffer range check
+    // step 5: keep z0(D + j), j < hop; o0 is the output index of slot 0
+    // (may be < 0); stores past len are dropped by the buffer range check
     if (active) {
-        const int64_t obase = int64_t(it.first_block) * hop;
-        const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, it.channel)) + obase * EO,
-                                  (cd.len - obase) * EO);
-        const int o0 = team * hop + t - d;   // output index of slot 0, may be < 0
+        if constexpr (CARRY) {
+            // hop = 12 T, D = 2 T: the kept samples are exactly slots 2..13
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int j = t + T * v - d;        // index within the block's kept samples
-            Out<S, F32OUT>::st(yr, unsigned(j) < unsigned(hop) ? (o0 + T * v) * EO : kOutOfRange, a[v]);
+            for (int v = 2; v < 14; ++v) Out<S, F32OUT>::st(yr, (o0 + T * v) * EO, a[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int j = t + T * v - d;        // index within the block's kept samples
+                Out<S, F32OUT>::st(yr, unsigned(j) < unsigned(hop) ? (o0 + T * v) * EO : kOutOfRange, a[v]);
+            }
         }
     }
 }
 
-// Consecutive items [i, end) of size N: twiddles loaded once, and the next
-// item's input is requested before the current one is filtered so its
-// latency hides behind the arithmetic.  Returns the first index not done.
-template <int LOG2N, Storage S, bool F32OUT>
-__device__ int run_items(const LaunchArgs &A, int i, int end, float2 *lds, float *vlds, WgState &ws) {
+// One span: blocks [first, first + n) of one channel, filtered by the
+// workgroup's G = 4096/N teams.  Team g takes the contiguous sub-run
+// [first + g n / G, first + (g+1) n / G) and the teams step through their
+// sub-runs together.  Consecutive blocks of a team share N - hop input
+// samples; when hop = 3N/4 (CARRY) they are exactly register slots 12..15 of
+// one block and 0..3 of the next, so only the 12 new slots are read from
+// memory and the 4 shared ones wait in LDS (cl: 4 values per thread; each
+// thread reads back only what it wrote, so no barrier is needed).
+template <int LOG2N, Storage S, bool F32OUT, bool CARRY>
+__device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp, const ChannelDev &cd,
+                                         const TwReg<LOG2N> &tw, float2 *lds, const float *vlds, float2 *cl) {
     using Sh = Shape<LOG2N>;
+    constexpr int N = Sh::N, T = Sh::T;
+    constexpr int G = kThreads / T;
+    constexpr int EI = Io<S>::kBytes;
+    constexpr int EO = Out<S, F32OUT>::kBytes;
     const int tid = threadIdx.x;
-    const int team = tid / Sh::T;
-    const int t = tid - team * Sh::T;
+    const int team = tid / T;
+    const int t = tid - team * T;
+    float2 *L = lds + team * lds_pad(N);
+    const int hop = cd.hop;
+    const int n = sp.n_blocks;
+    const int lo = int((int64_t(team) * n) / G);
+    const int cnt = int((int64_t(team + 1) * n) / G) - lo;
+    const int steps = (n + G - 1) / G;
+
+    // input resource from the span's first segment start (clipped at 0)
+    const int64_t s0 = int64_t(sp.first_block) * hop - (N - hop);
+    const int64_t clip = s0 > 0 ? s0 : 0;
+    const auto xr = make_rsrc(static_cast<const char *>(ld_uniform(A.x, sp.channel)) + clip * EI,
+                              (cd.len - clip) * EI);
+    const int64_t ob = int64_t(sp.first_block) * hop;
+    const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, sp.channel)) + ob * EO, (cd.len - ob) * EO);
+    const int jb = int(s0 - clip) + lo * hop + t;     // sample of slot 0 of the team's first block, rel. to xr
+
+    // step 1 for the team's first block: all 16 slots; samples before 0 read 0
+    float2 a[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int j = jb + T * v;
+        a[v] = Io<S>::ld(xr, j >= 0 ? j * EI : kOutOfRange);
+    }
+    for (int s = 0; s < steps; ++s) {
+        const int b = lo + s;                              // block within the span
+        const bool active = s < cnt;
+        const int64_t m = int64_t(sp.first_block) + b;
+        int k1 = ld_uniform(A.sched, cd.sched_begin).k1;   // last entry with from_block <= m
+        for (int e = 1; e < cd.sched_count; ++e) {
+            const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
+            if (sd.from_block <= m) k1 = sd.k1;
+        }
+        const bool more = s + 1 < steps;                   // workgroup-uniform
+        // For hop = 3N/4 every sample of slots 4..15 of a block after the
+        // channel's block 0 lies at index >= 0, so no zero-history test.
+        const int jn = jb + (s + 1) * hop;                 // slot 0 of the next block
+        if constexpr (CARRY) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cl[v * kThreads + tid] = a[12 + v];
+        }
+        filter_block<LOG2N, S, F32OUT, CARRY>(a, A, cd, k1, active, yr, b * hop + t - ((N - hop) >> 1), tw, L,
+                                              vlds, t);
+        if (more) {
+            if constexpr (CARRY) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a[v] = cl[v * kThreads + tid];
+#pragma unroll
+                for (int v = 4; v < 16; ++v) a[v] = Io<S>::ld(xr, (jn + T * v) * EI);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int j = jn + T * v;
+                    a[v] = Io<S>::ld(xr, j >= 0 ? j * EI : kOutOfRange);
+                }
+            }
+        }
+    }
+}
+
+// Consecutive spans [i, end) of size N: twiddles loaded once.  Returns the
+// first span index not done.
+template <int LOG2N, Storage S, bool F32OUT>
+__device__ int run_spans(const LaunchArgs &A, int i, int end, float2 *lds, float *vlds, float2 *cl, WgState &ws) {
+    using Sh = Shape<LOG2N>;
+    const int t = threadIdx.x % Sh::T;
     TwReg<LOG2N> tw;
     tw.load(Tw{make_rsrc(A.tw, int64_t(kTwiddleN) * 8)}, t);
-
-    WorkItem it = load_item(A, i);
-    ChannelDev cd = load_channel(A, it.channel);
-#if VBW_PREFETCH
-    // two register sets take turns: while one item is filtered the next
-    // item's input is in flight into the other (no copies between them)
-    float2 xa[16], xb[16];
-    gather<LOG2N, S>(xa, A, it, cd, team, t);
-    for (;;) {
-        int in = i + 1;
-        bool more = in < end && load_item(A, in).log2n == LOG2N;
-        WorkItem itb = it;
-        ChannelDev cdb = cd;
-        if (more) {
-            itb = load_item(A, in);
-            cdb = load_channel(A, itb.channel);
-            gather<LOG2N, S>(xb, A, itb, cdb, team, t);
+    for (; i < end; ++i) {
+        const WorkItem sp = load_item(A, i);
+        if (sp.log2n != LOG2N) break;
+        const ChannelDev cd = load_channel(A, sp.channel);
+        // stage this channel's V in LDS (workgroup-uniform decision)
+        if (cd.v_offset != ws.v_offset || cd.lv != ws.lv) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < cd.lv; q += kThreads) vlds[q] = A.v[cd.v_offset + q];
+            __syncthreads();
+            ws.v_offset = cd.v_offset;
+            ws.lv = cd.lv;
         }
-        filter_item<LOG2N, S, F32OUT>(xa, A, it, cd, tw, lds, vlds, ws);
-        if (!more) return in;
-        i = in;
-        in = i + 1;
-        more = in < end && load_item(A, in).log2n == LOG2N;
-        if (more) {
-            it = load_item(A, in);
-            cd = load_channel(A, it.channel);
-            gather<LOG2N, S>(xa, A, it, cd, team, t);
-        }
-        filter_item<LOG2N, S, F32OUT>(xb, A, itb, cdb, tw, lds, vlds, ws);
-        if (!more) return in;
-        i = in;
+        if (4 * cd.hop == 3 * Sh::N) run_span<LOG2N, S, F32OUT, true>(A, sp, cd, tw, lds, vlds, cl);
+        else run_span<LOG2N, S, F32OUT, false>(A, sp, cd, tw, lds, vlds, cl);
     }
-#else
-    float2 cur[16];
-    for (;;) {
-        gather<LOG2N, S>(cur, A, it, cd, team, t);
-        filter_item<LOG2N, S, F32OUT>(cur, A, it, cd, tw, lds, vlds, ws);
-        const int in = i + 1;
-        if (!(in < end && load_item(A, in).log2n == LOG2N)) return in;
-        i = in;
-        it = load_item(A, i);
-        cd = load_channel(A, it.channel);
-    }
-#endif
+    return i;
 }
 
-// Persistent launch: workgroup w filters items [wg_begin[w], wg_begin[w+1]),
-// a contiguous, cost-balanced range (consecutive blocks of a channel stay on
-// one CU, so the overlap each block re-reads is still in its caches).
+// Persistent launch: workgroup w filters spans [wg_begin[w], wg_begin[w+1]),
+// contiguous block ranges of equal estimated cost (consecutive blocks of a
+// channel stay on one CU).
 template <int LOG2N, Storage S, bool F32OUT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(VBW_WAVES_PER_EU, 8)))
 void ols_fft_kernel(const LaunchArgs A) {
     __shared__ float2 lds[kLdsValues];
     __shared__ float vlds[kVCap];
+    __shared__ float2 clds[4 * kThreads];
     WgState ws;
     const int w = blockIdx.x;
     int i = ld_uniform(A.wg_begin, w);
     const int end = ld_uniform(A.wg_begin, w + 1);
     while (i < end) {
         if constexpr (LOG2N != 0) {
-            i = run_items<LOG2N, S, F32OUT>(A, i, end, lds, vlds, ws);
+            i = run_spans<LOG2N, S, F32OUT>(A, i, end, lds, vlds, clds, ws);
+            if (i < end) i = end;   // every span of this launch has N = 2^LOG2N
         } else {
             switch (load_item(A, i).log2n) {
-                case 4: i = run_items<4, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 5: i = run_items<5, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 6: i = run_items<6, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 7: i = run_items<7, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 8: i = run_items<8, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 9: i = run_items<9, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 10: i = run_items<10, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 11: i = run_items<11, S, F32OUT>(A, i, end, lds, vlds, ws); break;
-                case 12: i = run_items<12, S, F32OUT>(A, i, end, lds, vlds, ws); break;
+                case 4: i = run_spans<4, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 5: i = run_spans<5, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 6: i = run_spans<6, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 7: i = run_spans<7, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 8: i = run_spans<8, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 9: i = run_spans<9, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 10: i = run_spans<10, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 11: i = run_spans<11, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+                case 12: i = run_spans<12, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
                 default: i = end; break;
             }
         }

@@ -48,6 +48,17 @@ hipError_t dev_alloc(void **p, size_t bytes) {
     return hipMalloc(p, bytes);
 }
 
+// Test hook: VBW_MAX_WORKGROUPS=k caps every persistent launch at k
+// workgroups, so that small inputs give each workgroup long spans.
+int wg_count(size_t tiles, size_t resident) {
+    size_t n = std::min(tiles, resident);
+    if (const char *s = std::getenv("VBW_MAX_WORKGROUPS")) {
+        const long k = std::atol(s);
+        if (k > 0) n = std::min(n, size_t(k));
+    }
+    return int(std::max<size_t>(1, n));
+}
+
 bool is_pow2(int32_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
 int ilog2(int32_t n) {
@@ -105,7 +116,8 @@ struct vbw_plan_s {
     std::vector<vbw_channel> ch;
     std::vector<float> v32;
     std::vector<Sched> sched;
-    std::vector<WorkItem> items;
+    std::vector<WorkItem> items;     // 4096-value tiles: up to 4096/N consecutive blocks
+    std::vector<WorkItem> work;      // device work list of every launch variant (tiles or spans)
     int32_t dtype = VBW_C64;
     int32_t engine = VBW_ENGINE_FFT;
     uint32_t flags = 0;
@@ -119,7 +131,7 @@ struct vbw_plan_s {
     int device = 0;
     WorkItem *d_items = nullptr;
     int32_t *d_wg_begin = nullptr;
-    std::vector<int32_t> wg_begin;   // concatenated per-launch workgroup item ranges
+    std::vector<int32_t> wg_begin;   // concatenated per-launch workgroup ranges of `work`
     // Launch variants: each is a list of persistent launches (one per N group,
     // or one launch of the kernel that dispatches on N), each with its own
     // workgroup count and item partition.
@@ -224,21 +236,46 @@ void build_items(vbw_plan_s *p) {
                      [](const WorkItem &a, const WorkItem &b) { return a.log2n < b.log2n; });
 }
 
-// Split items [b, e) into n_wg contiguous ranges of equal estimated cost and
-// append the n_wg + 1 range boundaries to wg_begin; returns their offset.  A
-// workgroup always works through a whole 4096-value tile, so an item costs
-// about log2(N) FFT passes plus a fixed part for loads, multiply and stores.
-int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg) {
+// A span's input and output offsets are 32-bit byte offsets from its base.
+constexpr int64_t kMaxSpanSamples = int64_t(1) << 26;
+
+// Split tiles [b, e) into n_wg contiguous ranges of equal estimated cost and
+// append the workgroups' work to p->work and their n_wg + 1 boundaries to
+// wg_begin; returns the offset of those boundaries.  A tile costs about
+// log2(N) FFT passes plus a fixed part for loads, multiply and stores.  With
+// `spans`, consecutive tiles of one channel inside a workgroup's range merge
+// into one span, so a team filters a run of consecutive blocks and can carry
+// the overlap from one block to the next; otherwise the tiles are kept.
+int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg, bool spans) {
     const size_t n = e - b;
     std::vector<double> pre(n + 1, 0.0);
     for (size_t i = 0; i < n; ++i) pre[i + 1] = pre[i] + (p->items[b + i].log2n + 2.0);
-    const int off = int(p->wg_begin.size());
+    std::vector<size_t> cut(size_t(n_wg) + 1, n);
     size_t i = 0;
-    for (int w = 0; w <= n_wg; ++w) {
+    for (int w = 0; w < n_wg; ++w) {
         const double target = pre[n] * double(w) / double(n_wg);
         while (i < n && pre[i] < target) ++i;
-        p->wg_begin.push_back(int32_t(b + (w == n_wg ? n : i)));
+        cut[size_t(w)] = i;
     }
+    const int off = int(p->wg_begin.size());
+    for (int w = 0; w < n_wg; ++w) {
+        const size_t first = p->work.size();
+        p->wg_begin.push_back(int32_t(first));
+        for (size_t t = b + cut[size_t(w)]; t < b + cut[size_t(w) + 1]; ++t) {
+            const WorkItem &it = p->items[t];
+            if (spans && p->work.size() > first) {
+                WorkItem &last = p->work.back();
+                const vbw_channel &ch = p->ch[size_t(it.channel)];
+                if (last.channel == it.channel && last.first_block + last.n_blocks == it.first_block &&
+                    int64_t(last.n_blocks + it.n_blocks) * ch.hop + ch.n <= kMaxSpanSamples) {
+                    last.n_blocks += it.n_blocks;
+                    continue;
+                }
+            }
+            p->work.push_back(it);
+        }
+    }
+    p->wg_begin.push_back(int32_t(p->work.size()));
     return off;
 }
 
@@ -253,6 +290,7 @@ vbw::Storage storage_of(int32_t dtype) {
 void build_variants(vbw_plan_s *p, int n_cu) {
     p->variants.clear();
     p->wg_begin.clear();
+    p->work.clear();
     const vbw::Storage st = storage_of(p->dtype);
     const bool f32 = (p->flags & VBW_F32_OUT) != 0;
     // contiguous groups of equal N
@@ -270,8 +308,8 @@ void build_variants(vbw_plan_s *p, int n_cu) {
     if (p->engine == VBW_ENGINE_GEMM) {
         for (int drop = 0; drop < 2; ++drop) {
             const int per = std::max(1, vbw::ols_gemm_wg_per_cu(st, f32) - drop);
-            const int n_wg = int(std::max<size_t>(1, std::min<size_t>(p->items.size(), size_t(n_cu) * per)));
-            p->variants.push_back({{-1, partition_items(p, 0, p->items.size(), n_wg), n_wg}});
+            const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per);
+            p->variants.push_back({{-1, partition_items(p, 0, p->items.size(), n_wg, false), n_wg}});
         }
         p->variant = 0;
         return;
@@ -280,20 +318,16 @@ void build_variants(vbw_plan_s *p, int n_cu) {
         std::vector<vbw_plan_s::LaunchGroup> v;
         if (generic) {
             const int per = std::max(1, vbw::ols_fft_wg_per_cu(0, st, f32) - occupancy_drop);
-            const int n_wg = int(std::max<size_t>(1, std::min<size_t>(p->items.size(), size_t(n_cu) * per)));
-            v.push_back({0, partition_items(p, 0, p->items.size(), n_wg), n_wg});
+            const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per);
+            v.push_back({0, partition_items(p, 0, p->items.size(), n_wg, true), n_wg});
             return v;
         }
-        // split the CUs between N groups in proportion to their cost so the
-        // launches finish together when they overlap
-        double total = 0;
-        for (auto &g : groups)
-            for (size_t i = g.first; i < g.second; ++i) total += p->items[i].log2n + 2.0;
+        // one launch per N, in order on the stream, each filling the chip
         for (auto &g : groups) {
             const int lg = p->items[g.first].log2n;
             const int per = std::max(1, vbw::ols_fft_wg_per_cu(lg, st, f32) - occupancy_drop);
-            const int n_wg = int(std::max<size_t>(1, std::min<size_t>(g.second - g.first, size_t(n_cu) * per)));
-            v.push_back({lg, partition_items(p, g.first, g.second, n_wg), n_wg});
+            const int n_wg = wg_count(g.second - g.first, size_t(n_cu) * per);
+            v.push_back({lg, partition_items(p, g.first, g.second, n_wg, true), n_wg});
         }
         return v;
     };
@@ -384,8 +418,6 @@ vbw_status setup_device(vbw_plan_s *p) {
     if (e != hipSuccess) return from_hip(e);
     p->host_only = false;
     void *d = nullptr;
-    if ((e = dev_alloc(&d, p->items.size() * sizeof(WorkItem))) != hipSuccess) return from_hip(e);
-    p->d_items = static_cast<WorkItem *>(d);
     if ((e = dev_alloc(&d, std::max<size_t>(1, p->v32.size()) * sizeof(float))) != hipSuccess) return from_hip(e);
     p->d_v = static_cast<float *>(d);
     if ((e = dev_alloc(&d, vbw::kTwiddleN * sizeof(float2))) != hipSuccess) return from_hip(e);
@@ -394,6 +426,8 @@ vbw_status setup_device(vbw_plan_s *p) {
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess)
         return from_hip(e);
     build_variants(p, n_cu);
+    if ((e = dev_alloc(&d, std::max<size_t>(1, p->work.size()) * sizeof(WorkItem))) != hipSuccess) return from_hip(e);
+    p->d_items = static_cast<WorkItem *>(d);
     if ((e = dev_alloc(&d, std::max<size_t>(1, p->wg_begin.size()) * sizeof(int32_t))) != hipSuccess)
         return from_hip(e);
     p->d_wg_begin = static_cast<int32_t *>(d);
@@ -408,8 +442,8 @@ vbw_status setup_device(vbw_plan_s *p) {
 
     std::vector<float> tw(2 * vbw::kTwiddleN);
     fill_twiddles(vbw::kTwiddleN, tw.data());
-    if (!p->items.empty() &&
-        (e = hipMemcpy(p->d_items, p->items.data(), p->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice)) != hipSuccess)
+    if (!p->work.empty() &&
+        (e = hipMemcpy(p->d_items, p->work.data(), p->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice)) != hipSuccess)
         return from_hip(e);
     if (!p->v32.empty() &&
         (e = hipMemcpy(p->d_v, p->v32.data(), p->v32.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
@@ -516,7 +550,7 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
     a.sched = reinterpret_cast<const SchedDev *>(p->d_dyn + nch * (sizeof(ChannelDev) + 2 * sizeof(void *)));
     a.v = p->d_v;
     a.tw = p->d_tw;
-    a.n_items = int32_t(p->items.size());
+    a.n_items = int32_t(p->work.size());
     a.wg_begin = p->d_wg_begin;
     a.n_wg = 0;
     a.prune = (p->flags & VBW_NO_PRUNE) ? 0 : 1;

@@ -36,8 +36,10 @@ struct SchedDev {
     int32_t pad;
 };
 
-// One workgroup's work: `n_blocks` consecutive blocks of one channel.
-// n_blocks <= 4096 / N so the blocks fill one 4096-value tile.
+// A run of `n_blocks` consecutive blocks of one channel.  The matrix-core
+// engine takes tiles (n_blocks <= 4096 / N, one 4096-value tile); the FFT
+// engine takes spans of any length (the team of one block walks through a
+// contiguous part of the span).
 struct WorkItem {
     int32_t channel;
     int32_t first_block;

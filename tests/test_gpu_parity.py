@@ -151,6 +151,37 @@ def test_edge_shapes_every_n(mixed):
     say("worst dB", worst)
 
 
+@pytest.mark.parametrize("cap", [1, 3, 7])
+def test_long_spans_every_block(monkeypatch, cap):
+    """Few workgroups (the VBW_MAX_WORKGROUPS hook) give each one long spans:
+    every team walks through a run of consecutive blocks, carrying the
+    overlap in registers when hop = 3N/4 (and reloading it otherwise).
+    Ragged tails, runs of unequal length per team, and bandwidth changes that
+    fall inside a team's run; every block is checked."""
+    monkeypatch.setenv("VBW_MAX_WORKGROUPS", str(cap))
+    rng = np.random.default_rng(100 + cap)
+    specs, sched = [], {}
+    for n, nb in ((16, 700), (64, 300), (256, 150), (1024, 60), (4096, 21)):
+        k1 = max(1, n // 8)
+        sched[len(specs)] = [(nb // 3, max(1, n // 2 - 5)), (nb // 3 + 1, max(1, n // 16)), (2 * nb // 3, k1 + 1)]
+        specs.append((n, 3 * n // 4, 3, k1, nb * (3 * n // 4) + 5, (n, 3)))
+        specs.append((n, n // 2, 3, k1, (nb // 2) * (n // 2) + 1, (n, 3)))
+    v_sets = v_for({s[5] for s in specs})
+    xs = [crandn(rng, s[4]) for s in specs]
+    say("long spans, workgroups per launch <=", cap)
+    ys = filter_full(specs, v_sets, xs, schedules=sched)
+    for ci, (spec, x, y) in enumerate(zip(specs, xs, ys)):
+        entries = [(0, spec[3])] + sched.get(ci, [])
+        ref = oracle_full(spec, v_sets, x, entries)
+        e = ols.error_db(y, ref)
+        assert e <= FP32_DB, (spec, e)
+        n, hop = spec[0], spec[1]
+        for m in range(1, -(-spec[4] // hop)):
+            sl = slice(m * hop, min(spec[4], (m + 1) * hop))
+            eb = ols.error_db(y[sl], ref[sl])
+            assert eb <= FP32_DB + 10, (spec, m, eb)
+
+
 def test_bandwidth_schedule_on_device():
     rng = np.random.default_rng(9)
     n, hop, lv = 1024, 768, 16
