@@ -30,6 +30,7 @@
 
 #include <utility>
 
+#include "fft_small.h"
 #include "vbw_internal.h"
 
 #ifndef VBW_WAVES_PER_EU
@@ -39,134 +40,9 @@
 namespace vbw {
 namespace {
 
+using namespace fft;
+
 typedef float f2v __attribute__((ext_vector_type(2)));
-
-// ---------------------------------------------------------------- complex ops
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
-    return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
-}
-__device__ __forceinline__ float2 cmulc(float2 a, float2 w) {  // a * conj(w)
-    return make_float2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
-}
-template <bool INV> __device__ __forceinline__ float2 tmul(float2 a, float2 w) {
-    return INV ? cmulc(a, w) : cmul(a, w);
-}
-// a * (-j) forward, a * (+j) inverse
-template <bool INV> __device__ __forceinline__ float2 rotj(float2 a) {
-    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
-}
-
-// cos and sin of 2 pi e / 16, e < 16 (float32 nearest of the exact values).
-__host__ __device__ constexpr float c16(int e) {
-    constexpr float c[16] = {
-        1.0f, 0.923879532511286756f, 0.707106781186547524f, 0.382683432365089772f,
-        0.0f, -0.382683432365089772f, -0.707106781186547524f, -0.923879532511286756f,
-        -1.0f, -0.923879532511286756f, -0.707106781186547524f, -0.382683432365089772f,
-        0.0f, 0.382683432365089772f, 0.707106781186547524f, 0.923879532511286756f};
-    return c[e & 15];
-}
-__host__ __device__ constexpr float s16(int e) { return c16(e + 12); }  // sin x = cos(x - pi/2)
-
-// a * w16^E with w16 = exp(-j 2 pi / 16) (forward) or its conjugate (inverse).
-template <bool INV, int E> __device__ __forceinline__ float2 w16mul(float2 a) {
-    constexpr int e = E & 15;
-    if constexpr (e == 0) {
-        return a;
-    } else if constexpr (e == 4) {
-        return rotj<INV>(a);
-    } else if constexpr (e == 8) {
-        return make_float2(-a.x, -a.y);
-    } else if constexpr (e == 12) {
-        return rotj<!INV>(a);
-    } else if constexpr ((e & 1) == 0) {
-        // +-sqrt(1/2) (+-1 +- j): two adds and two multiplies
-        constexpr float h = 0.707106781186547524f;
-        constexpr float c = c16(e);
-        constexpr float s = INV ? s16(e) : -s16(e);
-        // (x + j y)(c + j s) with |c| = |s| = h
-        const float p = (c > 0 ? a.x : -a.x) - (s > 0 ? a.y : -a.y);
-        const float q = (s > 0 ? a.x : -a.x) + (c > 0 ? a.y : -a.y);
-        return make_float2(h * p, h * q);
-    } else {
-        constexpr float c = c16(e);
-        constexpr float s = INV ? s16(e) : -s16(e);
-        return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
-    }
-}
-
-// ------------------------------------------------------------- small DFTs
-// In place, natural order in and out: a[s] <- sum_r a[r] w_R^{r s}.
-template <bool INV> __device__ __forceinline__ void dft2(float2 &a0, float2 &a1) {
-    const float2 t = a0;
-    a0 = cadd(t, a1);
-    a1 = csub(t, a1);
-}
-
-template <bool INV> __device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
-    const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
-    const float2 t2 = cadd(a1, a3), t3 = rotj<INV>(csub(a1, a3));
-    a0 = cadd(t0, t2);
-    a2 = csub(t0, t2);
-    a1 = cadd(t1, t3);
-    a3 = csub(t1, t3);
-}
-
-template <bool INV, int R2, int S1> __device__ __forceinline__ void tw16_step(float2 (&a)[16]) {
-    a[R2 + 4 * S1] = w16mul<INV, R2 * S1>(a[R2 + 4 * S1]);
-}
-
-// 16 = 4 x 4: r = 4 r1 + r2, s = s1 + 4 s2.
-template <bool INV> __device__ __forceinline__ void dft16(float2 (&a)[16]) {
-#pragma unroll
-    for (int r2 = 0; r2 < 4; ++r2) dft4<INV>(a[r2], a[4 + r2], a[8 + r2], a[12 + r2]);
-    // slot r2 + 4 s1 now holds the inner DFT over r1 at s1; twiddle w16^{r2 s1}
-    tw16_step<INV, 1, 1>(a); tw16_step<INV, 1, 2>(a); tw16_step<INV, 1, 3>(a);
-    tw16_step<INV, 2, 1>(a); tw16_step<INV, 2, 2>(a); tw16_step<INV, 2, 3>(a);
-    tw16_step<INV, 3, 1>(a); tw16_step<INV, 3, 2>(a); tw16_step<INV, 3, 3>(a);
-#pragma unroll
-    for (int s1 = 0; s1 < 4; ++s1) dft4<INV>(a[4 * s1], a[4 * s1 + 1], a[4 * s1 + 2], a[4 * s1 + 3]);
-    // slot 4 s1 + s2 holds Y(s1 + 4 s2): transpose the 4 x 4 register grid
-    float2 b[16];
-#pragma unroll
-    for (int s1 = 0; s1 < 4; ++s1)
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) b[s1 + 4 * s2] = a[4 * s1 + s2];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) a[i] = b[i];
-}
-
-// 8 = 4 x 2: r = 2 r1 + r2, s = s1 + 4 s2.
-template <bool INV> __device__ __forceinline__ void dft8(float2 (&a)[8]) {
-    dft4<INV>(a[0], a[2], a[4], a[6]);
-    dft4<INV>(a[1], a[3], a[5], a[7]);
-    a[3] = w16mul<INV, 2>(a[3]);
-    a[5] = w16mul<INV, 4>(a[5]);
-    a[7] = w16mul<INV, 6>(a[7]);
-#pragma unroll
-    for (int s1 = 0; s1 < 4; ++s1) dft2<INV>(a[2 * s1], a[2 * s1 + 1]);
-    float2 b[8];
-#pragma unroll
-    for (int s1 = 0; s1 < 4; ++s1) {
-        b[s1] = a[2 * s1];
-        b[s1 + 4] = a[2 * s1 + 1];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) a[i] = b[i];
-}
-
-template <int R, bool INV> __device__ __forceinline__ void dft_small(float2 (&a)[R]) {
-    if constexpr (R == 2) {
-        dft2<INV>(a[0], a[1]);
-    } else if constexpr (R == 4) {
-        dft4<INV>(a[0], a[1], a[2], a[3]);
-    } else if constexpr (R == 8) {
-        dft8<INV>(a);
-    } else {
-        dft16<INV>(a);
-    }
-}
 
 // ------------------------------------------------------------ storage
 // Channel data is read and written through buffer resources: 32-bit byte
@@ -615,8 +491,12 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
 #pragma unroll
             for (int v = 0; v < 4; ++v) cl[v * kThreads + tid] = a[12 + v];
         }
-        filter_block<LOG2N, S, F32OUT, CARRY>(a, A, cd, k1, active, yr, b * hop + t - ((N - hop) >> 1), tw, L,
-                                              vlds, t);
+        // a team that is exactly one wave skips the blocks past its run; smaller
+        // teams share a wave and larger ones share barriers, so they compute
+        // (and do not store) an idle block
+        if (T != 64 || active)
+            filter_block<LOG2N, S, F32OUT, CARRY>(a, A, cd, k1, active, yr, b * hop + t - ((N - hop) >> 1), tw, L,
+                                                  vlds, t);
         if (more) {
             if constexpr (CARRY) {
 #pragma unroll
