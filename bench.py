@@ -254,6 +254,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "channels": len(w.channels), "total_samples": total,
+                   "total_blocks": plan.query(vbw.Q_TOTAL_BLOCKS),
                    "n": c0.n if args.config != 3 else "mixed", "hop": c0.hop if args.config != 3 else "3N/4",
                    "storage": dtype, "engine": args.engine, "variant": plan.query(vbw.Q_VARIANT),
                    "description": w.description},

@@ -76,10 +76,14 @@ template <> struct Io<Storage::C64> {
     }
 };
 
-__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // quiet NaN
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// Two float32 to packed 16-bit, round to nearest even (one v_cvt_pk_* each).
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16_rne(float2 v) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{v.x, v.y}, bf2v));
+}
+__device__ __forceinline__ uint32_t pack_f16_rne(float2 v) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{v.x, v.y}, h2v));
 }
 
 template <> struct Io<Storage::F16> {
@@ -104,10 +108,9 @@ template <Storage S, bool F32OUT> struct Out {
         if constexpr (kBytes == 8) {
             __builtin_amdgcn_raw_buffer_store_b64(u2v{__float_as_uint(v.x), __float_as_uint(v.y)}, r, off, 0, kStorePolicy);
         } else if constexpr (S == Storage::F16) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __float22half2_rn(v)), r, off, 0, kStorePolicy);
+            __builtin_amdgcn_raw_buffer_store_b32(pack_f16_rne(v), r, off, 0, kStorePolicy);
         } else {
-            __builtin_amdgcn_raw_buffer_store_b32(f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16), r, off, 0,
-                                                  kStorePolicy);
+            __builtin_amdgcn_raw_buffer_store_b32(pack_bf16_rne(v), r, off, 0, kStorePolicy);
         }
     }
 };

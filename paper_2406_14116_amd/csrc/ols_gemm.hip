@@ -148,10 +148,15 @@ template <> struct GIo<Storage::BF16> {
     }
 };
 
-__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// Two float32 to packed 16-bit, round to nearest even (one v_cvt_pk_* each).
+typedef float gf2v __attribute__((ext_vector_type(2)));
+typedef __bf16 gbf2v __attribute__((ext_vector_type(2)));
+typedef _Float16 gh2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16_rne(float re, float im) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(gf2v{re, im}, gbf2v));
+}
+__device__ __forceinline__ uint32_t pack_f16_rne(float re, float im) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(gf2v{re, im}, gh2v));
 }
 
 template <Storage S, bool F32OUT> __device__ __forceinline__ void gstore(__amdgpu_buffer_rsrc_t r, int off, float re,
@@ -159,11 +164,9 @@ template <Storage S, bool F32OUT> __device__ __forceinline__ void gstore(__amdgp
     if constexpr (F32OUT) {
         __builtin_amdgcn_raw_buffer_store_b64(u2v{__float_as_uint(re), __float_as_uint(im)}, r, off, 0, kNT);
     } else if constexpr (S == Storage::F16) {
-        const uint32_t u = uint32_t(__builtin_bit_cast(uint16_t, (_Float16)re)) |
-                           (uint32_t(__builtin_bit_cast(uint16_t, (_Float16)im)) << 16);
-        __builtin_amdgcn_raw_buffer_store_b32(u, r, off, 0, kNT);
+        __builtin_amdgcn_raw_buffer_store_b32(pack_f16_rne(re, im), r, off, 0, kNT);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(f32_to_bf16_rne(re) | (f32_to_bf16_rne(im) << 16), r, off, 0, kNT);
+        __builtin_amdgcn_raw_buffer_store_b32(pack_bf16_rne(re, im), r, off, 0, kNT);
     }
 }
 

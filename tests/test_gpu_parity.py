@@ -411,3 +411,28 @@ def test_config4_storage_variants(storage, bound, engine):
                         n_random=4, tol=FP32_DB if engine == "fft" else GEMM_COMPUTE_DB)
     say(storage, engine, "compute-only dB max/median", max(dbs), float(np.median(dbs)))
     p32.close()
+
+
+@pytest.mark.parametrize("engine", ["fft", "gemm"])
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_16bit_store_is_nearest_even_of_float32_result(storage, engine):
+    """The 16-bit output equals the float32 output (VBW_F32_OUT plan, same
+    arithmetic) rounded to nearest even, bit for bit: the store conversion
+    adds one rounding and nothing else."""
+    w = wl.config4(storage=storage, n_channels=4)
+    xs = harness.upload_inputs(w, storage)
+    ys16 = harness.alloc_outputs(w, storage)
+    ys32 = harness.alloc_outputs(w, storage, f32_out=True)
+    p16 = vbw.Plan.from_workload(w, engine=engine)
+    p32 = vbw.Plan.from_workload(w, engine=engine, flags=vbw.F32_OUT)
+    run_plan(p16, xs, ys16)
+    run_plan(p32, xs, ys32)
+    tdt = torch.float16 if storage == "f16" else torch.bfloat16
+    for c in range(len(w.channels)):
+        want = torch.view_as_real(ys32[c].cpu()).to(tdt).view(torch.int16)
+        got = ys16[c].cpu().view(torch.int16)
+        bad = int((want != got).sum())
+        say(storage, engine, "channel", c, "mismatching 16-bit values", bad)
+        assert bad == 0
+    p16.close()
+    p32.close()
