@@ -426,6 +426,15 @@ vbw_status setup_device(vbw_plan_s *p) {
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess)
         return from_hip(e);
     build_variants(p, n_cu);
+    // Test hook: VBW_VARIANT=k fixes the launch variant (the autotuner then
+    // keeps it), so tests can run every variant.
+    if (const char *v = std::getenv("VBW_VARIANT")) {
+        const int k = std::atoi(v);
+        if (*v && k >= 0 && size_t(k) < p->variants.size()) {
+            p->variant = k;
+            p->tuned = true;
+        }
+    }
     if ((e = dev_alloc(&d, std::max<size_t>(1, p->work.size()) * sizeof(WorkItem))) != hipSuccess) return from_hip(e);
     p->d_items = static_cast<WorkItem *>(d);
     if ((e = dev_alloc(&d, std::max<size_t>(1, p->wg_begin.size()) * sizeof(int32_t))) != hipSuccess)

@@ -257,9 +257,11 @@ def test_graph_replay_matches_eager():
     pg.close()
 
 
-def test_autotuned_variants_agree():
-    """Every launch variant (per-N launches, one launch dispatching on N, two
-    occupancies) computes the same thing; the autotuner keeps one of them."""
+def test_every_launch_variant_and_the_autotuner(monkeypatch):
+    """Every launch variant of a mixed-N plan (per-N launches, one launch
+    dispatching on N; two occupancies each) against the oracle, forced one at
+    a time through the VBW_VARIANT hook, eagerly and replayed from a graph;
+    then the autotuner keeps one of them."""
     rng = np.random.default_rng(6)
     specs = [(256, 192, 8, 20, 90000, (256, 8)), (1024, 768, 16, 100, 300000, (1024, 16)),
              (2048, 1536, 16, 300, 200000, (2048, 16)), (512, 384, 8, 50, 50000, (512, 8))]
@@ -268,13 +270,32 @@ def test_autotuned_variants_agree():
     xs = [torch.from_numpy(crandn(rng, s[4])).cuda() for s in specs]
     ref = [ols.channel_hfso(x.cpu().numpy().astype(np.complex128), s[0], s[1], v_sets[s[5]], [(0, s[3])])
            for x, s in zip(xs, specs)]
+    p = vbw.Plan(chans, pool)
+    n_var = p.query(vbw.Q_N_VARIANTS)
+    assert n_var == 4
+    p.close()
+    stream = torch.cuda.Stream()
+    for k in range(n_var):
+        monkeypatch.setenv("VBW_VARIANT", str(k))
+        for flags in (0, vbw.GRAPH):
+            p = vbw.Plan(chans, pool, flags=flags)
+            assert p.query(vbw.Q_VARIANT) == k
+            for rep in range(2):
+                with torch.cuda.stream(stream):
+                    ys = [torch.full_like(x, complex(np.nan, np.nan)) for x in xs]
+                    p.filter(xs, ys, stream)
+                stream.synchronize()
+                worst = max(ols.error_db(y.cpu().numpy(), r) for y, r in zip(ys, ref))
+                say("variant", k, "flags", flags, "call", rep, "worst dB", worst)
+                assert worst <= FP32_DB
+            p.close()
+    monkeypatch.delenv("VBW_VARIANT")
     p = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE)
-    assert p.query(vbw.Q_N_VARIANTS) == 4
     ys = [torch.empty_like(x) for x in xs]
     run_plan(p, xs, ys)
     chosen = p.query(vbw.Q_VARIANT)
     say("autotune chose variant", chosen, "grid", p.query(vbw.Q_GRID))
-    assert 0 <= chosen < 4
+    assert 0 <= chosen < n_var
     for y, r in zip(ys, ref):
         assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
     run_plan(p, xs, ys)                      # tuned plan, second call
