@@ -155,7 +155,7 @@ const char *vbw_strerror(vbw_status status);
 /* Host-side introspection, for tests and tooling. */
 typedef enum vbw_query {
     VBW_Q_N_CHANNELS = 0,
-    VBW_Q_N_ITEMS = 1,         /* work items in the launch */
+    VBW_Q_N_ITEMS = 1,         /* 4096-value tiles (up to 4096/N consecutive blocks) in the work list */
     VBW_Q_TOTAL_BLOCKS = 2,    /* sum over channels of ceil(len/M) */
     VBW_Q_TOTAL_SAMPLES = 3,   /* sum over channels of len */
     VBW_Q_WORKGROUP = 4,       /* threads per workgroup */
