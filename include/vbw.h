@@ -76,6 +76,7 @@ typedef enum vbw_engine {
 #define VBW_F32_OUT    (1u << 2)  /* write float32 output for 16-bit input */
 #define VBW_HOST_ONLY  (1u << 3)  /* validate and build host tables only; no device use */
 #define VBW_AUTOTUNE   (1u << 4)  /* time the launch variants on the first vbw_filter */
+#define VBW_STREAM     (1u << 5)  /* successive vbw_filter calls continue one stream (FFT engine) */
 
 /* One channel.  `reserved` must be 0. */
 typedef struct vbw_channel {
@@ -112,12 +113,17 @@ typedef struct vbw_plan_s *vbw_plan_t;
  * len, a non-finite V, an unknown dtype/engine/flag or nonzero reserved
  * field; VBW_ERANGE when k1 < 1 or k2 = k1 + L_V - 1 > N/2 - 1 (the one
  * exception is the all-pass L_V = 0, k1 = N/2 + 1); VBW_EUNSUPPORTED for the
- * GEMM engine with float32 storage or any channel with N != 256;
- * VBW_ENOMEM / VBW_EDEVICE from HIP.
+ * GEMM engine with float32 storage, any channel with N != 256, or
+ * VBW_STREAM; VBW_ENOMEM / VBW_EDEVICE from HIP.  With VBW_STREAM every
+ * channel's len must be 0 or a multiple of M that is at least N - M (else
+ * VBW_EINVAL): a call then carries whole blocks and at least the history the
+ * next call needs.
  * On error *out is set to NULL. */
 vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out);
 
 /* Change channel `channel`'s bandwidth from block `from_block` on
+ * (on a VBW_STREAM plan blocks are counted from the start of the stream, not
+ * of the call)
  * (Sec. III-B: only the integer edge k1 changes; V is reused, nothing is
  * recomputed).  Block m uses the entry with the largest from_block <= m; an
  * entry with an equal from_block is replaced.  O(entries) host work, no device
@@ -135,6 +141,13 @@ vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
  * hipStream_t (NULL: the null stream).  Asynchronous: no host
  * synchronisation except when pointer or schedule tables must be re-uploaded
  * while an earlier upload is still in flight.
+ * With VBW_STREAM the calls continue one stream per channel (Sec. II: the
+ * input is one unbounded sequence cut into blocks): a call's block 0 reads
+ * the previous call's last N - M input samples instead of zeros, the band
+ * schedule counts blocks from the start of the stream, and the output of a
+ * sequence of calls equals that of one call over the concatenated input.  The
+ * stream state lives on the device and advances in stream order, so calls may
+ * be queued (or replayed from a graph) without host synchronisation.
  * With VBW_AUTOTUNE the first call also times every launch variant on these
  * buffers (blocking; the outputs are the filter's outputs all the same) and
  * keeps the fastest for the plan's lifetime.  With VBW_GRAPH and a non-null
@@ -144,6 +157,13 @@ vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
  * VBW_EUNSUPPORTED for a VBW_HOST_ONLY plan; VBW_EDEVICE from HIP. */
 vbw_status vbw_filter(vbw_plan_t plan, const void *const *x, void *const *y,
                       void *stream);
+
+/* Restart every channel's stream of a VBW_STREAM plan (Sec. II framing):
+ * zero history and block counters, stream-ordered on `stream` (a hipStream_t,
+ * NULL: the null stream).  The next vbw_filter behaves like the plan's first.
+ * Errors: VBW_EINVAL (NULL plan or a plan without VBW_STREAM);
+ * VBW_EUNSUPPORTED for a VBW_HOST_ONLY plan; VBW_EDEVICE from HIP. */
+vbw_status vbw_stream_reset(vbw_plan_t plan, void *stream);
 
 /* Release the plan and its device tables (NULL is a no-op).  Synchronizes
  * with work the plan has queued. */

@@ -469,18 +469,36 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
     const int64_t ob = int64_t(sp.first_block) * hop;
     const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, sp.channel)) + ob * EO, (cd.len - ob) * EO);
     const int jb = int(s0 - clip) + lo * hop + t;     // sample of slot 0 of the team's first block, rel. to xr
+    // The N - hop samples before sample 0: zeros, or the stream's history
+    // (the previous call's last N - hop input samples) on a streaming plan.
+    const int hl = N - hop;
+    const auto hr = A.hist ? make_rsrc(static_cast<const char *>(A.hist) + cd.hist_off * EI, int64_t(hl) * EI)
+                           : make_rsrc(A.tw, 0);
+    const int64_t mb = A.block0 ? ld_uniform(A.block0, sp.channel) : 0;   // stream block of the call's block 0
 
-    // step 1 for the team's first block: all 16 slots; samples before 0 read 0
+    // step 1: all 16 slots of the block whose slot 0 is sample j0 (rel. to xr);
+    // samples before 0 read 0, and on a streaming plan are then replaced by
+    // the history (only for segments that start before sample 0)
     float2 a[16];
+    auto gather = [&](int j0) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int j = jb + T * v;
-        a[v] = Io<S>::ld(xr, j >= 0 ? j * EI : kOutOfRange);
-    }
+        for (int v = 0; v < 16; ++v) {
+            const int j = j0 + T * v;
+            a[v] = Io<S>::ld(xr, j >= 0 ? j * EI : kOutOfRange);
+        }
+        if (A.hist != nullptr && j0 - t < 0) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int j = j0 + T * v;
+                if (j < 0) a[v] = Io<S>::ld(hr, (j + hl) * EI);
+            }
+        }
+    };
+    gather(jb);
     for (int s = 0; s < steps; ++s) {
         const int b = lo + s;                              // block within the span
         const bool active = s < cnt;
-        const int64_t m = int64_t(sp.first_block) + b;
+        const int64_t m = mb + int64_t(sp.first_block) + b;
         int k1 = ld_uniform(A.sched, cd.sched_begin).k1;   // last entry with from_block <= m
         for (int e = 1; e < cd.sched_count; ++e) {
             const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
@@ -488,7 +506,7 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
         }
         const bool more = s + 1 < steps;                   // workgroup-uniform
         // For hop = 3N/4 every sample of slots 4..15 of a block after the
-        // channel's block 0 lies at index >= 0, so no zero-history test.
+        // channel's block 0 lies at index >= 0, so no history test.
         const int jn = jb + (s + 1) * hop;                 // slot 0 of the next block
         if constexpr (CARRY) {
 #pragma unroll
@@ -507,11 +525,7 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
 #pragma unroll
                 for (int v = 4; v < 16; ++v) a[v] = Io<S>::ld(xr, (jn + T * v) * EI);
             } else {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int j = jn + T * v;
-                    a[v] = Io<S>::ld(xr, j >= 0 ? j * EI : kOutOfRange);
-                }
+                gather(jn);
             }
         }
     }

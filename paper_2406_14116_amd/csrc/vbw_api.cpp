@@ -26,7 +26,7 @@ using vbw::WorkItem;
 namespace {
 
 constexpr int kMaxSchedPerChannel = 4096;
-constexpr uint32_t kKnownFlags = VBW_NO_PRUNE | VBW_GRAPH | VBW_F32_OUT | VBW_HOST_ONLY | VBW_AUTOTUNE;
+constexpr uint32_t kKnownFlags = VBW_NO_PRUNE | VBW_GRAPH | VBW_F32_OUT | VBW_HOST_ONLY | VBW_AUTOTUNE | VBW_STREAM;
 
 vbw_status from_hip(hipError_t e) {
     if (e == hipSuccess) return VBW_OK;
@@ -143,6 +143,9 @@ struct vbw_plan_s {
     std::vector<std::vector<LaunchGroup>> variants;
     bool tuned = false;
     float *d_v = nullptr;
+    void *d_hist = nullptr;           // streaming: N - hop history samples per channel
+    int64_t *d_block0 = nullptr;      // streaming: stream block index of each channel's next block
+    int64_t hist_bytes = 0;
     float2 *d_tw = nullptr;
     unsigned char *d_dyn = nullptr;   // ChannelDev[nch] | x[nch] | y[nch] | SchedDev[cap]
     size_t dyn_cap_sched = 0;
@@ -193,6 +196,14 @@ vbw_status validate_desc(const vbw_plan_desc *d) {
         if (!k1_in_range(ch.n, ch.lv, ch.k1)) range = VBW_ERANGE;
     }
     if (range != VBW_OK) return range;
+    if (d->flags & VBW_STREAM) {
+        // a call carries whole blocks and at least one block's history
+        for (int32_t c = 0; c < d->n_channels; ++c) {
+            const vbw_channel &ch = d->channels[c];
+            if (ch.len != 0 && (ch.len % ch.hop != 0 || ch.len < ch.n - ch.hop)) return VBW_EINVAL;
+        }
+        if (d->engine == VBW_ENGINE_GEMM) return VBW_EUNSUPPORTED;
+    }
     if (d->engine == VBW_ENGINE_GEMM) {
         // matrix-core engine: 16-bit storage and N = 256 only
         if (d->dtype == VBW_C64) return VBW_EUNSUPPORTED;
@@ -353,6 +364,8 @@ void free_device(vbw_plan_s *p) {
     if (p->d_items) (void)hipFree(p->d_items);
     if (p->d_wg_begin) (void)hipFree(p->d_wg_begin);
     if (p->d_v) (void)hipFree(p->d_v);
+    if (p->d_hist) (void)hipFree(p->d_hist);
+    if (p->d_block0) (void)hipFree(p->d_block0);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_dyn) (void)hipFree(p->d_dyn);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
@@ -365,6 +378,8 @@ void free_device(vbw_plan_s *p) {
     p->d_items = nullptr;
     p->d_wg_begin = nullptr;
     p->d_v = nullptr;
+    p->d_hist = nullptr;
+    p->d_block0 = nullptr;
     p->d_tw = nullptr;
     p->d_dyn = nullptr;
     p->h_stage = nullptr;
@@ -422,6 +437,20 @@ vbw_status setup_device(vbw_plan_s *p) {
     p->d_v = static_cast<float *>(d);
     if ((e = dev_alloc(&d, vbw::kTwiddleN * sizeof(float2))) != hipSuccess) return from_hip(e);
     p->d_tw = static_cast<float2 *>(d);
+    if (p->flags & VBW_STREAM) {
+        const int64_t eb = p->dtype == VBW_C64 ? 8 : 4;
+        p->hist_bytes = 0;
+        for (const auto &ch : p->ch) p->hist_bytes += int64_t(ch.n - ch.hop) * eb;
+        if ((e = dev_alloc(&d, size_t(std::max<int64_t>(16, p->hist_bytes)))) != hipSuccess) return from_hip(e);
+        p->d_hist = d;
+        if ((e = dev_alloc(&d, p->ch.size() * sizeof(int64_t))) != hipSuccess) return from_hip(e);
+        p->d_block0 = static_cast<int64_t *>(d);
+        // the stream starts from zero history at block 0
+        if ((e = vbw::launch_stream_reset(p->d_hist, p->hist_bytes, p->d_block0, int(p->ch.size()), nullptr)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(nullptr)) != hipSuccess)
+            return from_hip(e);
+    }
     int n_cu = 0;
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess)
         return from_hip(e);
@@ -519,8 +548,11 @@ vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipSt
     void **hy = reinterpret_cast<void **>(h + nch * (sizeof(ChannelDev) + sizeof(void *)));
     SchedDev *hs = reinterpret_cast<SchedDev *>(h + nch * (sizeof(ChannelDev) + 2 * sizeof(void *)));
     int32_t so = 0;
+    int64_t ho = 0;
     for (size_t c = 0; c < nch; ++c) {
         const vbw_channel &ch = p->ch[c];
+        hc[c].hist_off = ho;
+        ho += ch.n - ch.hop;
         hc[c].len = ch.len;
         hc[c].n = ch.n;
         hc[c].hop = ch.hop;
@@ -561,13 +593,18 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
     a.tw = p->d_tw;
     a.n_items = int32_t(p->work.size());
     a.wg_begin = p->d_wg_begin;
+    a.hist = p->d_hist;
+    a.block0 = p->d_block0;
     a.n_wg = 0;
     a.prune = (p->flags & VBW_NO_PRUNE) ? 0 : 1;
     a.pad = 0;
     return a;
 }
 
-hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant) {
+// The filter launches of one variant; on a streaming plan `advance` then
+// moves every channel's history and block counter past this call (the
+// autotuner's trial runs leave them alone).
+hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant, bool advance = true) {
     vbw::LaunchArgs a = launch_args(p);
     for (const auto &g : p->variants[size_t(variant)]) {
         a.wg_begin = p->d_wg_begin + g.wg_off;
@@ -577,6 +614,8 @@ hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant) {
                                    : vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), f32, s);
         if (e != hipSuccess) return e;
     }
+    if (advance && (p->flags & VBW_STREAM))
+        return vbw::launch_stream_update(a, int(p->ch.size()), storage_of(p->dtype), p->d_hist, p->d_block0, s);
     return hipSuccess;
 }
 
@@ -593,10 +632,10 @@ vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
     float best = 0.f;
     int best_v = 0;
     for (size_t v = 0; e == hipSuccess && v < p->variants.size(); ++v) {
-        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch(p, s, int(v));
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch(p, s, int(v), false);
         float ms = 0.f;
         if (e == hipSuccess) e = hipEventRecord(a, s);
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(p, s, int(v));
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(p, s, int(v), false);
         if (e == hipSuccess) e = hipEventRecord(b, s);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
@@ -708,6 +747,20 @@ vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *
     if (st == VBW_OK) st = from_hip(hipEventRecord(p->done_evt, s));
     if (prev != p->device) (void)hipSetDevice(prev);
     return st;
+}
+
+vbw_status vbw_stream_reset(vbw_plan_t p, void *stream) {
+    if (!p || !(p->flags & VBW_STREAM)) return VBW_EINVAL;
+    if (p->host_only) return VBW_EUNSUPPORTED;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return from_hip(e);
+    if (prev != p->device && (e = hipSetDevice(p->device)) != hipSuccess) return from_hip(e);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    e = vbw::launch_stream_reset(p->d_hist, p->hist_bytes, p->d_block0, int(p->ch.size()), s);
+    if (e == hipSuccess) e = hipEventRecord(p->done_evt, s);
+    if (prev != p->device) (void)hipSetDevice(prev);
+    return from_hip(e);
 }
 
 void vbw_destroy(vbw_plan_t p) {

@@ -18,7 +18,7 @@ constexpr int kTwiddleN = 1 << kMaxLog2N;                 // one table of w_4096
 __host__ __device__ constexpr int lds_pad(int p) { return p + (p >> 4); }
 constexpr int kLdsValues = lds_pad(kTilePoints);
 
-// Per-channel constants (device table, 32 bytes).
+// Per-channel constants (device table, 40 bytes).
 struct ChannelDev {
     int64_t len;
     int32_t n;
@@ -27,6 +27,7 @@ struct ChannelDev {
     int32_t v_offset;
     int32_t sched_begin;   // first schedule entry of this channel
     int32_t sched_count;   // entries, sorted by from_block, first has from_block 0
+    int64_t hist_off;      // streaming: first of this channel's N - hop history samples
 };
 
 // One bandwidth-schedule entry (16 bytes).
@@ -58,6 +59,8 @@ struct LaunchArgs {
     const void *const *x;    // per-channel input pointers
     void *const *y;          // per-channel output pointers
     const int32_t *wg_begin; // workgroup w owns items [wg_begin[w], wg_begin[w+1])
+    const void *hist;        // streaming: history pool (storage format), else nullptr
+    const int64_t *block0;   // streaming: stream block index of each channel's block 0, else nullptr
     int32_t n_items;
     int32_t n_wg;            // workgroups in the (persistent) launch
     int32_t prune;           // nonzero: stopband-pruned last forward / first inverse pass
@@ -76,6 +79,13 @@ hipError_t launch_ols_fft(const LaunchArgs &args, int log2n_fixed, Storage in,
 // Matrix-core engine (ols_gemm.hip): N = 256, 16-bit storage only.
 int ols_gemm_wg_per_cu(Storage in, bool f32_out);
 hipError_t launch_ols_gemm(const LaunchArgs &args, Storage in, bool f32_out, hipStream_t stream);
+
+// Streaming continuation (stream.hip): after a call, every channel's history
+// becomes the last N - hop input samples of the call and its block counter
+// advances by len / hop; reset zeroes both.
+hipError_t launch_stream_update(const LaunchArgs &args, int n_channels, Storage in, void *hist, int64_t *block0,
+                                hipStream_t stream);
+hipError_t launch_stream_reset(void *hist, int64_t hist_bytes, int64_t *block0, int n_channels, hipStream_t stream);
 
 // Streaming copy of `bytes` bytes (copy.hip); src and dst 16-byte aligned.
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int n_cu, hipStream_t stream);

@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vbw.h")
 VBW_OK, VBW_EINVAL, VBW_ERANGE, VBW_ENOMEM, VBW_EDEVICE, VBW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DTYPES = {"c64": 0, "f16": 1, "bf16": 2}
 ENGINES = {"fft": 0, "gemm": 1}
-NO_PRUNE, GRAPH, F32_OUT, HOST_ONLY, AUTOTUNE = 1, 2, 4, 8, 16
+NO_PRUNE, GRAPH, F32_OUT, HOST_ONLY, AUTOTUNE, STREAM = 1, 2, 4, 8, 16, 32
 (Q_N_CHANNELS, Q_N_ITEMS, Q_TOTAL_BLOCKS, Q_TOTAL_SAMPLES, Q_WORKGROUP, Q_LDS_BYTES, Q_GRID, Q_VARIANT,
  Q_N_VARIANTS) = range(9)
 
@@ -73,6 +73,8 @@ def lib():
         L.vbw_copy.restype = ctypes.c_int
         L.vbw_twiddle_table.argtypes = [ctypes.c_int32, P]
         L.vbw_twiddle_table.restype = ctypes.c_int
+        L.vbw_stream_reset.argtypes = [P, P]
+        L.vbw_stream_reset.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -190,6 +192,17 @@ class Plan:
             stream = torch.cuda.current_stream()
         s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         self.filter_ptrs([t.data_ptr() for t in xs], [t.data_ptr() for t in ys], s)
+
+    def stream_reset(self, stream=None) -> None:
+        """Restart every channel's stream (STREAM plans) on ``stream``
+        (default: torch's current stream)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        rc = lib().vbw_stream_reset(self.handle, s or None)
+        if rc != VBW_OK:
+            raise VbwError(rc, "vbw_stream_reset")
 
     def query(self, q: int) -> int:
         return int(lib().vbw_plan_query(self.handle, int(q)))

@@ -189,3 +189,26 @@ def test_plan_copies_descriptors():
     v[:] = 0.0
     chans[0]["len"] = 1
     assert p.query(vbw.Q_TOTAL_SAMPLES) == 65536
+
+
+def test_stream_plan_validation():
+    """A streaming plan's calls carry whole blocks and at least the N - hop
+    samples of history the next call needs; the matrix-core engine does not
+    stream; reset is refused where there is no device stream state."""
+    ok = host_plan([chan(length=192 * 10), chan(n=1024, hop=768, lv=16, k1=100, length=0)], flags=vbw.STREAM)
+    with pytest.raises(vbw.VbwError) as e:
+        ok.stream_reset(0)
+    assert e.value.status == vbw.VBW_EUNSUPPORTED
+    ok.close()
+    for bad in (chan(length=192 * 10 + 1), chan(n=256, hop=2, lv=8, k1=24, length=200)):
+        with pytest.raises(vbw.VbwError) as e:
+            host_plan([bad], flags=vbw.STREAM)
+        assert e.value.status == vbw.VBW_EINVAL, bad
+    with pytest.raises(vbw.VbwError) as e:
+        host_plan([chan(length=192 * 10)], flags=vbw.STREAM, dtype="f16", engine="gemm")
+    assert e.value.status == vbw.VBW_EUNSUPPORTED
+    plain = host_plan([chan()])
+    with pytest.raises(vbw.VbwError) as e:
+        plain.stream_reset(0)
+    assert e.value.status == vbw.VBW_EINVAL
+    plain.close()

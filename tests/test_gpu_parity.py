@@ -457,3 +457,77 @@ def test_16bit_store_is_nearest_even_of_float32_result(storage, engine):
         assert bad == 0
     p16.close()
     p32.close()
+
+
+STREAM_SPECS = [  # (n, hop, lv, k1, blocks per call)
+    (256, 192, 8, 24, 9), (1024, 768, 16, 100, 7), (512, 256, 8, 40, 5), (64, 2, 3, 5, 40),
+    (4096, 3072, 32, 200, 2), (2048, 1536, 16, 300, 3), (16, 12, 2, 3, 50),
+]
+
+
+@pytest.mark.parametrize("storage", ["c64", "f16"])
+@pytest.mark.parametrize("flags", [0, vbw.GRAPH, vbw.NO_PRUNE])
+def test_stream_chunks_equal_one_shot(storage, flags):
+    """A streaming plan fed C consecutive chunks gives the output of one call
+    over the whole input (Sec. II: one unbounded input stream), with band
+    changes counted in stream blocks and falling in later chunks; then a reset
+    restarts the stream.  Bit for bit when both runs take the same inverse
+    (NO_PRUNE: whether a pass is pruned is decided per wave, and a wave's
+    blocks depend on how the launch is cut); within the float32 bar
+    otherwise."""
+    calls = 4
+    rng = np.random.default_rng(17)
+    v_sets = v_for({(s[0], s[2]) for s in STREAM_SPECS})
+    chunk = [s[4] * s[1] for s in STREAM_SPECS]
+    total = [c * calls for c in chunk]
+    mk = lambda lens: channels_from([(s[0], s[1], s[2], s[3], L, (s[0], s[2])) for s, L in zip(STREAM_SPECS, lens)],
+                                    v_sets)
+    sched = {ci: [(s[4] * 2 + 1, max(1, s[3] // 2)), (s[4] * 3, s[3])] for ci, s in enumerate(STREAM_SPECS)}
+    xs_full = [harness.host_to_storage(crandn(rng, L).astype(np.complex128), storage).cuda() for L in total]
+    ys_one = [torch.empty_like(x) for x in xs_full]
+    ys_str = [torch.full_like(x, float("nan")) if storage != "c64" else torch.full_like(x, complex(np.nan, np.nan))
+              for x in xs_full]
+    chans1, pool = mk(total)
+    p1 = vbw.Plan(chans1, pool, dtype=storage, flags=flags & vbw.NO_PRUNE)
+    chans_s, _ = mk(chunk)
+    ps = vbw.Plan(chans_s, pool, dtype=storage, flags=flags | vbw.STREAM)
+    for ci, entries in sched.items():
+        for frm, k1 in entries:
+            p1.set_bandwidth(ci, k1, frm)
+            ps.set_bandwidth(ci, k1, frm)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())     # inputs and NaN fills are ready
+    with torch.cuda.stream(stream):
+        p1.filter(xs_full, ys_one, stream)
+        for i in range(calls):
+            ps.filter([x[i * c:(i + 1) * c] for x, c in zip(xs_full, chunk)],
+                      [y[i * c:(i + 1) * c] for y, c in zip(ys_str, chunk)], stream)
+    stream.synchronize()
+    for ci, s in enumerate(STREAM_SPECS):
+        a = harness.storage_to_c128(ys_str[ci])
+        b = harness.storage_to_c128(ys_one[ci])
+        assert np.all(np.isfinite(a)), s
+        if flags & vbw.NO_PRUNE:
+            assert torch.equal(ys_str[ci].cpu().view(torch.int16 if storage != "c64" else torch.int64),
+                               ys_one[ci].cpu().view(torch.int16 if storage != "c64" else torch.int64)), s
+        else:
+            assert ols.error_db(a, b) <= FP32_DB, s
+    # the one-shot run against the oracle (schedule in stream blocks)
+    for ci in (1, 3):
+        s = STREAM_SPECS[ci]
+        x = harness.storage_to_c128(xs_full[ci])
+        ref = ols.channel_hfso(x, s[0], s[1], v_sets[(s[0], s[2])], [(0, s[3])] + sched[ci])
+        got = harness.storage_to_c128(ys_str[ci])
+        e = ols.error_db(got, ref)
+        say("stream", storage, flags, "channel", ci, "dB vs oracle", e)
+        assert e <= (FP32_DB if storage == "c64" else -60.0)
+    # restart: the next call is the stream's first chunk again
+    ys_again = [torch.empty_like(x[:c]) for x, c in zip(xs_full, chunk)]
+    with torch.cuda.stream(stream):
+        ps.stream_reset(stream)
+        ps.filter([x[:c] for x, c in zip(xs_full, chunk)], ys_again, stream)
+    stream.synchronize()
+    for ci, c in enumerate(chunk):
+        assert torch.equal(ys_again[ci].cpu(), ys_str[ci][:c].cpu()), STREAM_SPECS[ci]
+    p1.close()
+    ps.close()
