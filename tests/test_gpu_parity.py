@@ -531,3 +531,38 @@ def test_stream_chunks_equal_one_shot(storage, flags):
         assert torch.equal(ys_again[ci].cpu(), ys_str[ci][:c].cpu()), STREAM_SPECS[ci]
     p1.close()
     ps.close()
+
+
+def test_designed_filter_meets_paper_spec_on_gpu():
+    """The paper's example (Sec. IV): V from the minimax design for L = 33,
+    N = 128, M = 96, b_N in [48, 55]; the GPU path filters complex
+    exponentials so that stopband ones come out below 0.001 (-60 dB) and
+    passband ones within 0.001 of the input delayed by D, at every output
+    position of steady-state blocks, for b at both ends and the middle of the
+    range."""
+    from paper_2406_14116_amd import hfso_design as hd
+    n, m, dn = 128, 96, 16
+    r = hd.minimax_v(n, m, dn, (48, 55), k=1000)
+    assert r.delta <= 1e-3
+    d = (n - m) // 2
+    length = 20 * m
+    t = np.arange(length)
+    chans, xs, wants = [], [], []
+    for b_n in (48, 51, 55):
+        k1 = b_n - dn // 2 + 1
+        wp = (b_n - dn / 2) * 2 * np.pi / n
+        ws = (b_n + dn / 2) * 2 * np.pi / n
+        for w in (0.0, 0.5 * wp, wp, ws, 0.5 * (ws + np.pi), np.pi):
+            chans.append(dict(n=n, hop=m, lv=dn - 1, v_offset=0, k1=k1, len=length))
+            xs.append(torch.from_numpy(np.exp(1j * w * t).astype(np.complex64)).cuda())
+            wants.append(np.exp(1j * w * (t - d)) if w <= wp + 1e-12 else np.zeros(length))
+    p = vbw.Plan(chans, r.v)
+    ys = [torch.empty_like(x) for x in xs]
+    run_plan(p, xs, ys)
+    worst = 0.0
+    for y, want in zip(ys, wants):
+        err = np.max(np.abs(y.cpu().numpy()[2 * m:] - want[2 * m:]))
+        worst = max(worst, err)
+    say("designed filter: worst |error| on the GPU", worst, "dB", 20 * np.log10(worst))
+    assert worst <= 1e-3 + 1e-5
+    p.close()
