@@ -25,6 +25,8 @@ module computes them:
   program is solved by HiGHS on a growing set of grid points (each round adds
   the worst points of the full grid) until the full-grid maximum agrees with
   the program's value.
+* ``measure_ptvir_gpu`` -- the same responses measured on the GPU library:
+  one vbw_filter call over a grid of complex exponentials.
 * ``rates``          -- Table I: multiplications and additions per output
   sample, with the cheaper exponent multiplies of Sec. III-D when
   (L - 1)/N = 1/(2c).
@@ -34,7 +36,7 @@ module computes them:
   order and a few above it (which meet it too) the one with the fewest
   multiplications per output sample.
 
-Everything here is float64 on the host (scipy's HiGHS); it runs once per
+The design itself is float64 on the host (scipy's HiGHS); it runs once per
 design, not per sample.
 """
 from __future__ import annotations
@@ -290,3 +292,28 @@ def design(delta_p: float, delta_s: float, delta_over_pi: float, b_over_pi: tupl
                 break
     L, n, m, delta_n, br, r = results[nd]
     return Design(L=L, n=n, m=m, delta_n=delta_n, b_range=br, result=r, tried=tried)
+
+
+def measure_ptvir_gpu(n: int, m: int, k1: int, v, w, stream=None) -> np.ndarray:
+    """The responses G_j(w) (shape (M, K)) of the filter as the GPU library
+    actually runs it: one channel per frequency carries exp(j w t) for three
+    blocks, and output position j of block 2 (whose segment lies inside the
+    input) gives y[2M + j] exp(-j w (2M + j)) = G_j(w).  One vbw_filter call
+    evaluates the whole grid (float32 arithmetic)."""
+    import torch
+
+    from . import vbw
+    w = np.asarray(w, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    length = 3 * m
+    t = np.arange(length)
+    x = np.exp(1j * np.outer(w, t)).astype(np.complex64)          # (K, 3M)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    chans = [dict(n=n, hop=m, lv=v.size, v_offset=0, k1=k1, len=length) for _ in range(w.size)]
+    with vbw.Plan(chans, v) as plan:
+        plan.filter([xd[i] for i in range(w.size)], [yd[i] for i in range(w.size)], stream)
+        torch.cuda.synchronize()
+    y = yd.cpu().numpy().astype(np.complex128)
+    tt = 2 * m + np.arange(m)
+    return (y[:, tt] * np.exp(-1j * np.outer(w, tt))).T

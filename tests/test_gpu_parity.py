@@ -566,3 +566,19 @@ def test_designed_filter_meets_paper_spec_on_gpu():
     say("designed filter: worst |error| on the GPU", worst, "dB", 20 * np.log10(worst))
     assert worst <= 1e-3 + 1e-5
     p.close()
+
+
+def test_gpu_measured_ptvir_matches_evaluator():
+    """The PTVIR responses of every output position, measured by running
+    exponentials through the GPU library, equal the design module's evaluator
+    (which is itself pinned to the oracle's filter on the CPU)."""
+    from paper_2406_14116_amd import hfso_design as hd
+    n, m, k1, lv = 128, 96, 41, 15
+    v = np.linspace(0.99, 0.01, lv)
+    w = np.linspace(0.0, np.pi, 257)
+    a, c = hd.impulse_terms(n, m, k1, lv)
+    want = hd.ptvir(a + c @ v, n, m, w)
+    got = hd.measure_ptvir_gpu(n, m, k1, v.astype(np.float32).astype(np.float64), w)
+    err = np.max(np.abs(got - want))
+    say("GPU-measured vs evaluated PTVIR max |diff|", err)
+    assert err < 2e-5
