@@ -56,22 +56,23 @@ def traffic_from_profile(kernel: str, workload_key: str, engine: str):
     return float(t.group(1))
 
 
-def make_workload(cfg: int, storage: str):
+def make_workload(cfg: int, storage: str, real: bool = False):
     from paper_2406_14116_amd import workloads as wl
+    cd = "r32" if real else "c64"
     if cfg == 2:
-        return wl.config2(), "c64"
+        return wl.config2(), cd
     if cfg == 3:
-        return wl.config3(), "c64"
+        return wl.config3(), cd
     if cfg == 5:
-        return wl.config5(), "c64"
+        return wl.config5(), cd
     if cfg == 4:
         return wl.config4(storage=storage), storage
     raise SystemExit(f"config {cfg} is not a bench workload (2, 3, 4, 5)")
 
 
-def workload_key(cfg: int, storage: str, engine: str) -> str:
+def workload_key(cfg: int, storage: str, engine: str, real: bool = False) -> str:
     return {2: "fp32_64ch_n1024", 3: "batched_512ch_mixed", 5: "narrow_256ch_n4096",
-            4: f"{storage}_256ch_n256"}[cfg] + ("_gemm" if engine == "gemm" else "")
+            4: f"{storage}_256ch_n256"}[cfg] + ("_gemm" if engine == "gemm" else "") + ("_real" if real else "")
 
 
 def oracle_input(w, ci: int, dtype: str):
@@ -81,6 +82,8 @@ def oracle_input(w, ci: int, dtype: str):
     from paper_2406_14116_amd import workloads as wl
     if dtype == "c64":
         return wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128)
+    if dtype == "r32":      # real input: the float32 real parts, exactly
+        return wl.channel_samples(w, ci, dtype=np.complex64).real.astype(np.complex128)
     return wl.channel_samples(w, ci)
 
 
@@ -224,6 +227,8 @@ def main():
     ap.add_argument("--engine", choices=("fft", "gemm"), default="fft",
                     help="gemm: matrix-core DFTs (16-bit storage, N = 256: config 4)")
     ap.add_argument("--storage", choices=("f16", "bf16"), default="f16", help="config 4 storage")
+    ap.add_argument("--real", action="store_true",
+                    help="configs 2, 3, 5 on real float32 input (the real parts of the samples)")
     ap.add_argument("--stream-chunks", type=int, default=0,
                     help="filter every channel as one stream fed in this many calls per step "
                          "(VBW_STREAM; each call a whole number of blocks on fixed buffers)")
@@ -240,7 +245,7 @@ def main():
     import torch
     from paper_2406_14116_amd import harness, vbw
 
-    w, dtype = make_workload(args.config, args.storage)
+    w, dtype = make_workload(args.config, args.storage, args.real)
     log(f"bench: {w.name}: {len(w.channels)} channels, {w.total_samples()} samples, storage {dtype}")
     if args.copy_calibration:
         nbytes = w.total_samples() * (8 if dtype == "c64" else 4)
@@ -282,7 +287,7 @@ def main():
     total = w.total_samples()
     bytes_per_sample = 16 if dtype == "c64" else 8
     achieved = total * bytes_per_sample / (kernel_ms * 1e-3) / 1e9
-    key = workload_key(args.config, dtype, args.engine)
+    key = workload_key(args.config, dtype, args.engine, args.real)
     kernel = "ols_gemm" if args.engine == "gemm" else "ols_fft"
     traffic = traffic_from_profile(kernel, key, args.engine)
 
@@ -300,7 +305,7 @@ def main():
     line = {
         "metric": METRIC,
         "value": total / (ms_per_step * 1e-3),
-        "unit": "complex samples/s",
+        "unit": "real samples/s" if dtype == "r32" else "complex samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -310,7 +315,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "channels": len(w.channels), "total_samples": total,
+        "config": {"workload": w.name + ("+real" if dtype == "r32" else ""), "channels": len(w.channels), "total_samples": total,
                    "total_blocks": plan.query(vbw.Q_TOTAL_BLOCKS),
                    "n": c0.n if args.config != 3 else "mixed", "hop": c0.hop if args.config != 3 else "3N/4",
                    "storage": dtype, "engine": args.engine, "variant": plan.query(vbw.Q_VARIANT),
@@ -324,7 +329,7 @@ def main():
         "accuracy_db": {"max": max(dbs) if dbs else None,
                         "median": float(np.median(dbs)) if dbs else None,
                         "channels_checked": len(dbs),
-                        "versus": "oracle on the stored float32 input" if dtype == "c64" else
+                        "versus": "oracle on the stored float32 input" if dtype in ("c64", "r32") else
                                   "oracle on the unquantized input (end to end: input and output rounding)"},
     }
     plan.close()

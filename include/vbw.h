@@ -26,6 +26,10 @@
  *   VBW_C64   -- two float32 per sample (8 bytes)
  *   VBW_CF16  -- two IEEE binary16 per sample (4 bytes)
  *   VBW_CBF16 -- two bfloat16 per sample (4 bytes)
+ *   VBW_R32   -- real input: one float32 per sample (4 bytes), real output.
+ *               The impulse response is real (eq. (8)), so the library
+ *               filters two consecutive real blocks as the real and imaginary
+ *               parts of one complex block.
  * Arithmetic is float32 in every case; 16-bit values are converted on load
  * and rounded to nearest-even on store.  With VBW_F32_OUT the output is
  * written as float32 pairs whatever the input storage.
@@ -61,7 +65,8 @@ typedef enum vbw_status {
 typedef enum vbw_dtype {
     VBW_C64 = 0,
     VBW_CF16 = 1,
-    VBW_CBF16 = 2
+    VBW_CBF16 = 2,
+    VBW_R32 = 3       /* real float32 samples in and out (FFT engine) */
 } vbw_dtype;
 
 typedef enum vbw_engine {

@@ -102,6 +102,17 @@ template <> struct Io<Storage::BF16> {
     }
 };
 
+// Real float32 samples (real input, real output).
+template <> struct Io<Storage::R32> {
+    static constexpr int kBytes = 4;
+    __device__ static float ld(__amdgpu_buffer_rsrc_t r, int off) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kLoadPolicy));
+    }
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, int off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, kStorePolicy);
+    }
+};
+
 template <Storage S, bool F32OUT> struct Out {
     static constexpr int kBytes = (S == Storage::C64 || F32OUT) ? 8 : 4;
     __device__ static void st(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
@@ -377,7 +388,7 @@ struct WgState {
 // forward DFT, HFSO multiply, inverse DFT, keep z0(D + j), j < hop.
 template <int LOG2N, Storage S, bool F32OUT, bool CARRY>
 __device__ __forceinline__ void filter_block(float2 (&a)[16], const LaunchArgs &A, const ChannelDev &cd, int k1,
-                                             bool active, __amdgpu_buffer_rsrc_t yr, int o0,
+                                             int keep, __amdgpu_buffer_rsrc_t yr, int o0,
                                              const TwReg<LOG2N> &tw, float2 *L, const float *vlds, int t) {
     using Sh = Shape<LOG2N>;
     constexpr int N = Sh::N, T = Sh::T;
@@ -419,8 +430,28 @@ __device__ __forceinline__ void filter_block(float2 (&a)[16], const LaunchArgs &
     }
 
     // step 5: keep z0(D + j), j < hop; o0 is the output index of slot 0
-    // (may be < 0); stores past len are dropped by the buffer range check
-    if (active) {
+    // (may be < 0); stores past len are dropped by the buffer range check.
+    // keep: bit 0 stores the block (real parts: the pair's first block),
+    // bit 1 the imaginary parts as the pair's second block (real input)
+    if constexpr (S == Storage::R32) {
+        if (keep) {
+            const bool kx = keep & 1, ky = keep & 2;
+            if constexpr (CARRY) {
+#pragma unroll
+                for (int v = 2; v < 14; ++v) {
+                    if (kx) Io<S>::st(yr, (o0 + T * v) * 4, a[v].x);
+                    if (ky) Io<S>::st(yr, (o0 + hop + T * v) * 4, a[v].y);
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const bool in = unsigned(t + T * v - d) < unsigned(hop);
+                    Io<S>::st(yr, in && kx ? (o0 + T * v) * 4 : kOutOfRange, a[v].x);
+                    Io<S>::st(yr, in && ky ? (o0 + hop + T * v) * 4 : kOutOfRange, a[v].y);
+                }
+            }
+        }
+    } else if (keep & 1) {
         if constexpr (CARRY) {
             // hop = 12 T, D = 2 T: the kept samples are exactly slots 2..13
 #pragma unroll
@@ -516,8 +547,8 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
         // teams share a wave and larger ones share barriers, so they compute
         // (and do not store) an idle block
         if (T != 64 || active)
-            filter_block<LOG2N, S, F32OUT, CARRY>(a, A, cd, k1, active, yr, b * hop + t - ((N - hop) >> 1), tw, L,
-                                                  vlds, t);
+            filter_block<LOG2N, S, F32OUT, CARRY>(a, A, cd, k1, active ? 1 : 0, yr, b * hop + t - ((N - hop) >> 1), tw,
+                                                  L, vlds, t);
         if (more) {
             if constexpr (CARRY) {
 #pragma unroll
@@ -526,6 +557,121 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
                 for (int v = 4; v < 16; ++v) a[v] = Io<S>::ld(xr, (jn + T * v) * EI);
             } else {
                 gather(jn);
+            }
+        }
+    }
+}
+
+// Real input (R32 storage).  The impulse response is real (eq. (8)), so two
+// real blocks filtered as the real and the imaginary parts of one complex
+// block come out as the real and imaginary parts of the result.  A team takes
+// pairs of consecutive blocks (2p, 2p+1), the first in the real parts, the
+// second in the imaginary parts, and walks through a contiguous run of pairs
+// (spans start at even blocks).  When hop = 3N/4 slots 0..3 of block 2p+2 are
+// slots 12..15 of block 2p+1 (carried in LDS) and slots 0..3 of block 2p+3
+// are slots 12..15 of block 2p+2 (already in registers): 24 new samples per
+// thread and pair.  A pair whose blocks fall under different band-schedule
+// entries is filtered twice, once per block.
+template <int LOG2N, bool F32OUT, bool CARRY>
+__device__ __forceinline__ void run_span_real(const LaunchArgs &A, const WorkItem &sp, const ChannelDev &cd,
+                                              const TwReg<LOG2N> &tw, float2 *lds, const float *vlds, float2 *cl) {
+    using Sh = Shape<LOG2N>;
+    using IoR = Io<Storage::R32>;
+    constexpr int N = Sh::N, T = Sh::T;
+    constexpr int G = kThreads / T;
+    constexpr int E = 4;
+    const int tid = threadIdx.x;
+    const int team = tid / T;
+    const int t = tid - team * T;
+    float2 *L = lds + team * lds_pad(N);
+    const int hop = cd.hop;
+    const int np = (sp.n_blocks + 1) >> 1;
+    const int lo = int((int64_t(team) * np) / G);
+    const int cnt = int((int64_t(team + 1) * np) / G) - lo;
+    const int steps = (np + G - 1) / G;
+
+    const int64_t s0 = int64_t(sp.first_block) * hop - (N - hop);
+    const int64_t clip = s0 > 0 ? s0 : 0;
+    const auto xr = make_rsrc(static_cast<const char *>(ld_uniform(A.x, sp.channel)) + clip * E,
+                              (cd.len - clip) * E);
+    const int64_t ob = int64_t(sp.first_block) * hop;
+    const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, sp.channel)) + ob * E, (cd.len - ob) * E);
+    const int hl = N - hop;
+    const auto hr = A.hist ? make_rsrc(static_cast<const char *>(A.hist) + cd.hist_off * E, int64_t(hl) * E)
+                           : make_rsrc(A.tw, 0);
+    const int64_t mb = A.block0 ? ld_uniform(A.block0, sp.channel) : 0;
+    const int jb = int(s0 - clip) + 2 * lo * hop + t;  // slot 0 of the first block of the team's first pair
+
+    float2 a[16];
+    // both blocks of the pair whose first block has slot 0 at sample j0 (rel. to xr)
+    auto gather_pair = [&](int j0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int jx = j0 + T * v, jy = jx + hop;
+            a[v].x = IoR::ld(xr, jx >= 0 ? jx * E : kOutOfRange);
+            a[v].y = IoR::ld(xr, jy >= 0 ? jy * E : kOutOfRange);
+        }
+        if (A.hist != nullptr && j0 - t < 0) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int jx = j0 + T * v, jy = jx + hop;
+                if (jx < 0) a[v].x = IoR::ld(hr, (jx + hl) * E);
+                if (jy < 0) a[v].y = IoR::ld(hr, (jy + hl) * E);
+            }
+        }
+    };
+    auto k1_of = [&](int64_t m) {   // last schedule entry with from_block <= m
+        int k1 = ld_uniform(A.sched, cd.sched_begin).k1;
+        for (int e = 1; e < cd.sched_count; ++e) {
+            const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
+            if (sd.from_block <= m) k1 = sd.k1;
+        }
+        return k1;
+    };
+    gather_pair(jb);
+    // one filter per iteration: a pair whose blocks need different k1 takes
+    // two iterations (pass 1 filters the re-gathered pair for its second block)
+    int s = 0, pass = 0;
+    while (s < steps) {
+        const int q = lo + s;                               // pair within the span
+        const bool active = s < cnt;
+        const int64_t ma = mb + int64_t(sp.first_block) + 2 * q;
+        const int k1a = k1_of(ma), k1b = k1_of(ma + 1);
+        const bool same = k1a == k1b;
+        // the second pass is taken by the whole wave (team <= one wave) or the
+        // whole workgroup (teams with workgroup barriers)
+        bool split;
+        if constexpr (Sh::WAVE_LOCAL) split = __any(!same);
+        else split = __syncthreads_or(!same);
+        if (CARRY && pass == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cl[v * kThreads + tid] = make_float2(a[12 + v].y, 0.f);
+        }
+        const int o0 = 2 * q * hop + t - (hl >> 1);
+        const int keep = !active ? 0 : pass ? (same ? 0 : 2) : (same ? 3 : 1);
+        if (T != 64 || active)
+            filter_block<LOG2N, Storage::R32, F32OUT, CARRY>(a, A, cd, pass ? k1b : k1a, keep, yr, o0, tw, L, vlds,
+                                                             t);
+        if (split && pass == 0) {
+            gather_pair(jb + 2 * s * hop);                  // the pair again, for its second block
+            pass = 1;
+            continue;
+        }
+        pass = 0;
+        ++s;
+        if (s < steps) {
+            const int jn = jb + 2 * s * hop;                // slot 0 of the next pair's first block
+            if constexpr (CARRY) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a[v].x = cl[v * kThreads + tid].x;
+#pragma unroll
+                for (int v = 4; v < 16; ++v) a[v].x = IoR::ld(xr, (jn + T * v) * E);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a[v].y = a[12 + v].x;
+#pragma unroll
+                for (int v = 4; v < 16; ++v) a[v].y = IoR::ld(xr, (jn + hop + T * v) * E);
+            } else {
+                gather_pair(jn);
             }
         }
     }
@@ -551,8 +697,13 @@ __device__ int run_spans(const LaunchArgs &A, int i, int end, float2 *lds, float
             ws.v_offset = cd.v_offset;
             ws.lv = cd.lv;
         }
-        if (4 * cd.hop == 3 * Sh::N) run_span<LOG2N, S, F32OUT, true>(A, sp, cd, tw, lds, vlds, cl);
-        else run_span<LOG2N, S, F32OUT, false>(A, sp, cd, tw, lds, vlds, cl);
+        if constexpr (S == Storage::R32) {
+            if (4 * cd.hop == 3 * Sh::N) run_span_real<LOG2N, F32OUT, true>(A, sp, cd, tw, lds, vlds, cl);
+            else run_span_real<LOG2N, F32OUT, false>(A, sp, cd, tw, lds, vlds, cl);
+        } else {
+            if (4 * cd.hop == 3 * Sh::N) run_span<LOG2N, S, F32OUT, true>(A, sp, cd, tw, lds, vlds, cl);
+            else run_span<LOG2N, S, F32OUT, false>(A, sp, cd, tw, lds, vlds, cl);
+        }
     }
     return i;
 }
@@ -636,6 +787,7 @@ template <Storage S, bool F32OUT> int occupancy_typed(int log2n) {
 int ols_fft_wg_per_cu(int log2n_fixed, Storage in, bool f32_out) {
     switch (in) {
         case Storage::C64: return occupancy_typed<Storage::C64, false>(log2n_fixed);
+        case Storage::R32: return occupancy_typed<Storage::R32, false>(log2n_fixed);
         case Storage::F16:
             return f32_out ? occupancy_typed<Storage::F16, true>(log2n_fixed)
                            : occupancy_typed<Storage::F16, false>(log2n_fixed);
@@ -651,6 +803,7 @@ hipError_t launch_ols_fft(const LaunchArgs &A, int log2n_fixed, Storage in, bool
     if (A.n_items <= 0) return hipSuccess;
     switch (in) {
         case Storage::C64: return launch_typed<Storage::C64, false>(A, log2n_fixed, stream);
+        case Storage::R32: return launch_typed<Storage::R32, false>(A, log2n_fixed, stream);
         case Storage::F16:
             return f32_out ? launch_typed<Storage::F16, true>(A, log2n_fixed, stream)
                            : launch_typed<Storage::F16, false>(A, log2n_fixed, stream);

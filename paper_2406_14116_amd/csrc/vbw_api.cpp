@@ -180,7 +180,8 @@ vbw_status validate_desc(const vbw_plan_desc *d) {
     if (!d || !d->channels || d->n_channels < 1 || d->n_v < 0 || (d->n_v > 0 && !d->v_pool))
         return VBW_EINVAL;
     if (d->reserved != 0 || (d->flags & ~kKnownFlags) != 0) return VBW_EINVAL;
-    if (d->dtype != VBW_C64 && d->dtype != VBW_CF16 && d->dtype != VBW_CBF16) return VBW_EINVAL;
+    if (d->dtype != VBW_C64 && d->dtype != VBW_CF16 && d->dtype != VBW_CBF16 && d->dtype != VBW_R32)
+        return VBW_EINVAL;
     if (d->engine != VBW_ENGINE_FFT && d->engine != VBW_ENGINE_GEMM) return VBW_EINVAL;
     for (int32_t i = 0; i < d->n_v; ++i)
         if (!std::isfinite(d->v_pool[i])) return VBW_EINVAL;
@@ -205,8 +206,8 @@ vbw_status validate_desc(const vbw_plan_desc *d) {
         if (d->engine == VBW_ENGINE_GEMM) return VBW_EUNSUPPORTED;
     }
     if (d->engine == VBW_ENGINE_GEMM) {
-        // matrix-core engine: 16-bit storage and N = 256 only
-        if (d->dtype == VBW_C64) return VBW_EUNSUPPORTED;
+        // matrix-core engine: 16-bit complex storage and N = 256 only
+        if (d->dtype == VBW_C64 || d->dtype == VBW_R32) return VBW_EUNSUPPORTED;
         for (int32_t c = 0; c < d->n_channels; ++c)
             if (d->channels[c].n != 256) return VBW_EUNSUPPORTED;
     }
@@ -225,7 +226,8 @@ void build_items(vbw_plan_s *p) {
         const vbw_channel &ch = p->ch[c];
         const int64_t nb = n_blocks_of(ch.len, ch.hop);
         const int lg = ilog2(ch.n);
-        const int per = vbw::kTilePoints / ch.n;
+        // real input filters blocks in pairs: tiles (and spans) start at even blocks
+        const int per = vbw::kTilePoints / ch.n * (p->dtype == VBW_R32 ? 2 : 1);
         p->total_blocks += nb;
         p->total_samples += ch.len;
         for (int64_t b = 0; b < nb; b += per) {
@@ -291,7 +293,10 @@ int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg, bool spans) {
 }
 
 vbw::Storage storage_of(int32_t dtype) {
-    return dtype == VBW_CF16 ? vbw::Storage::F16 : dtype == VBW_CBF16 ? vbw::Storage::BF16 : vbw::Storage::C64;
+    return dtype == VBW_CF16    ? vbw::Storage::F16
+           : dtype == VBW_CBF16 ? vbw::Storage::BF16
+           : dtype == VBW_R32   ? vbw::Storage::R32
+                                : vbw::Storage::C64;
 }
 
 // Candidate launch shapes (the autotuner times them; variant 0 is the default):

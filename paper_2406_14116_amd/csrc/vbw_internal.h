@@ -48,7 +48,7 @@ struct WorkItem {
     int32_t log2n;
 };
 
-enum class Storage : int { C64 = 0, F16 = 1, BF16 = 2 };
+enum class Storage : int { C64 = 0, F16 = 1, BF16 = 2, R32 = 3 };
 
 struct LaunchArgs {
     const WorkItem *items;

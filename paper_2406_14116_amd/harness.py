@@ -20,6 +20,8 @@ def host_to_storage(x: np.ndarray, dtype: str):
     torch = _torch()
     if dtype == "c64":
         return torch.from_numpy(np.ascontiguousarray(x.astype(np.complex64)))
+    if dtype == "r32":                      # real input: the real parts
+        return torch.from_numpy(np.ascontiguousarray(x.real.astype(np.float32)))
     pairs = np.stack([x.real, x.imag], axis=1).astype(np.float32)
     t = torch.from_numpy(np.ascontiguousarray(pairs))
     # float32 -> float16 / bfloat16 conversion rounds to nearest-even
@@ -32,12 +34,14 @@ def storage_to_c128(t) -> np.ndarray:
     t = t.detach().to("cpu")
     if t.dtype == torch.complex64:
         return t.numpy().astype(np.complex128)
+    if t.dtype == torch.float32 and t.dim() == 1:     # real storage
+        return t.numpy().astype(np.complex128)
     f = t.to(torch.float32).numpy().reshape(-1, 2).astype(np.float64)
     return f[:, 0] + 1j * f[:, 1]
 
 
 def upload_channel(w: wl.Workload, ch: int, dtype: str, device="cuda"):
-    x = wl.channel_samples(w, ch, dtype=np.complex128 if dtype != "c64" else np.complex64)
+    x = wl.channel_samples(w, ch, dtype=np.complex64 if dtype in ("c64", "r32") else np.complex128)
     return host_to_storage(x, dtype).to(device)
 
 
@@ -49,7 +53,9 @@ def alloc_outputs(w: wl.Workload, dtype: str, f32_out: bool = False, device="cud
     torch = _torch()
     outs = []
     for c in w.channels:
-        if dtype == "c64" or f32_out:
+        if dtype == "r32":
+            outs.append(torch.empty(c.length, dtype=torch.float32, device=device))
+        elif dtype == "c64" or f32_out:
             outs.append(torch.empty(c.length, dtype=torch.complex64, device=device))
         else:
             tdt = torch.float16 if dtype == "f16" else torch.bfloat16

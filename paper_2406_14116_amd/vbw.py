@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("VBW_LIBRARY", os.path.join(HERE, "libvbw.so"))
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vbw.h")
 
 VBW_OK, VBW_EINVAL, VBW_ERANGE, VBW_ENOMEM, VBW_EDEVICE, VBW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-DTYPES = {"c64": 0, "f16": 1, "bf16": 2}
+DTYPES = {"c64": 0, "f16": 1, "bf16": 2, "r32": 3}
 ENGINES = {"fft": 0, "gemm": 1}
 NO_PRUNE, GRAPH, F32_OUT, HOST_ONLY, AUTOTUNE, STREAM = 1, 2, 4, 8, 16, 32
 (Q_N_CHANNELS, Q_N_ITEMS, Q_TOTAL_BLOCKS, Q_TOTAL_SAMPLES, Q_WORKGROUP, Q_LDS_BYTES, Q_GRID, Q_VARIANT,
@@ -150,7 +150,7 @@ class Plan:
         chans = [dict(n=c.n, hop=c.hop, lv=c.lv, v_offset=offs[c.v_key], k1=c.k1, len=c.length)
                  for c in w.channels]
         if dtype is None:
-            dtype = {"c64": "c64", "c128": "c64", "f16": "f16", "bf16": "bf16"}[w.storage]
+            dtype = {"c64": "c64", "c128": "c64", "f16": "f16", "bf16": "bf16", "r32": "r32"}[w.storage]
         p = cls(chans, pool, dtype=dtype, engine=engine, flags=flags)
         for i, c in enumerate(w.channels):
             for frm, k1 in c.schedule:
@@ -179,9 +179,9 @@ class Plan:
             raise VbwError(rc, "vbw_filter")
 
     def filter(self, xs, ys, stream=None) -> None:
-        """Filter torch tensors: complex64 (c64 storage) or (len, 2) float16 /
-        bfloat16 (16-bit storage); outputs likewise, or (len, 2) float32 /
-        complex64 with F32_OUT.  Runs on ``stream`` (default: torch's current)."""
+        """Filter torch tensors: complex64 (c64 storage), (len, 2) float16 /
+        bfloat16 (16-bit storage) or 1-D float32 (r32, real input); outputs
+        likewise, or (len, 2) float32 / complex64 with F32_OUT.  Runs on ``stream`` (default: torch's current)."""
         import torch
         if len(xs) != self.n_channels or len(ys) != self.n_channels:
             raise ValueError("one input and one output tensor per channel")
