@@ -143,9 +143,10 @@ vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
  * (layout above); the host arrays x and y hold n_channels pointers and are
  * read during the call only.  The device buffers are caller-owned and must
  * stay valid until the work on `stream` completes.  `stream` is a
- * hipStream_t (NULL: the null stream).  Asynchronous: no host
- * synchronisation except when pointer or schedule tables must be re-uploaded
- * while an earlier upload is still in flight.
+ * hipStream_t (NULL: the null stream).  Asynchronous: new pointers or a
+ * changed schedule are uploaded, stream-ordered, into one of two per-call
+ * tables that take turns (one with VBW_GRAPH); the host waits only when the
+ * table's previous upload has not left its staging buffer yet.
  * With VBW_STREAM the calls continue one stream per channel (Sec. II: the
  * input is one unbounded sequence cut into blocks): a call's block 0 reads
  * the previous call's last N - M input samples instead of zeros, the band

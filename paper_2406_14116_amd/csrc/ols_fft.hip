@@ -7,13 +7,15 @@
 // (runs of consecutive blocks of one channel); every team takes a contiguous
 // part of the span, so when hop = 3N/4 the N/4 input samples one block shares
 // with the next are carried over instead of read again.
-// Per block (Sec. II, steps 1-4):
+// Per block (Sec. II, steps 1-5):
 //   1. gather: thread t loads segment samples t + (N/16) v, v < 16 (coalesced
-//      across the team; zero outside [0, len));
+//      across the team); samples past len read 0, samples before 0 read 0 or,
+//      on a streaming plan, the previous call's last N - M input samples;
 //   2. forward DFT as Stockham autosort passes: radix-16 passes, then one pass
 //      of radix 2/4/8 when log2 N is not a multiple of 4; passes exchange data
 //      through the padded LDS tile; the last pass leaves X(t + (N/16) v) in
-//      registers;
+//      registers and computes only the two outer sub-bands when the band ends
+//      below N/R (the others are stopband);
 //   3. multiply by H_R (Sec. III-B, eq. (6)): only the bin index decides
 //      between 1 (passband), V(r) (transition) and 0 (stopband); the 1/N of the
 //      inverse (eq. (4)) is folded in here;
@@ -22,6 +24,8 @@
 //   5. the linear phase exp(-j 2 pi k D / N) of eq. (5) is a circular delay by
 //      D = (N - M)/2, so the kept output samples N-M+j of the phased inverse are
 //      samples D + j of z0: thread t stores v where 0 <= t + (N/16) v - D < M.
+// Real input (R32 storage) runs two consecutive blocks through one complex
+// block, as its real and imaginary parts (the impulse response is real).
 // Twiddles come from one float32 table w_4096^r (generated in float64 on the
 // host, rounded to nearest).
 #include <hip/hip_runtime.h>

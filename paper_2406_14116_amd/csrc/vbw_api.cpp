@@ -147,13 +147,20 @@ struct vbw_plan_s {
     int64_t *d_block0 = nullptr;      // streaming: stream block index of each channel's next block
     int64_t hist_bytes = 0;
     float2 *d_tw = nullptr;
-    unsigned char *d_dyn = nullptr;   // ChannelDev[nch] | x[nch] | y[nch] | SchedDev[cap]
+    // Per-call tables, ChannelDev[nch] | x[nch] | y[nch] | SchedDev[cap] each:
+    // two of them taking turns (one in graph mode, whose graph holds the
+    // address), so that the host fills the next while the device may still be
+    // reading the last one from an earlier call
+    unsigned char *d_dyn = nullptr;
     size_t dyn_cap_sched = 0;
-    unsigned char *h_stage = nullptr; // pinned staging for d_dyn
+    size_t dyn_stride = 0;            // bytes per table (256-byte multiple)
+    int n_tables = 1;
+    int cur = 0;                      // table the next launch reads
+    unsigned char *h_stage = nullptr; // pinned staging, n_tables x dyn_stride
     size_t stage_bytes = 0;
-    hipEvent_t upload_evt = nullptr;
+    hipEvent_t upload_evt[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
     hipEvent_t done_evt = nullptr;
-    bool upload_pending = false;
     bool dyn_valid = false;
     bool sched_dirty = true;
     std::vector<const void *> last_x;
@@ -362,7 +369,8 @@ void free_device(vbw_plan_s *p) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(p->device);
     if (p->done_evt) (void)hipEventSynchronize(p->done_evt);
-    if (p->upload_evt) (void)hipEventSynchronize(p->upload_evt);
+    for (auto ev : p->upload_evt)
+        if (ev) (void)hipEventSynchronize(ev);
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -374,7 +382,8 @@ void free_device(vbw_plan_s *p) {
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_dyn) (void)hipFree(p->d_dyn);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
-    if (p->upload_evt) (void)hipEventDestroy(p->upload_evt);
+    for (auto ev : p->upload_evt)
+        if (ev) (void)hipEventDestroy(ev);
     if (p->done_evt) (void)hipEventDestroy(p->done_evt);
     (void)hipSetDevice(prev);
     p->graph_exec = nullptr;
@@ -388,7 +397,7 @@ void free_device(vbw_plan_s *p) {
     p->d_tw = nullptr;
     p->d_dyn = nullptr;
     p->h_stage = nullptr;
-    p->upload_evt = p->done_evt = nullptr;
+    p->upload_evt[0] = p->upload_evt[1] = p->done_evt = nullptr;
 }
 
 void fill_twiddles(int32_t n, float *out) {
@@ -402,7 +411,8 @@ void fill_twiddles(int32_t n, float *out) {
 
 vbw_status alloc_dyn(vbw_plan_s *p, size_t sched_cap) {
     void *d = nullptr, *h = nullptr;
-    const size_t bytes = p->dyn_bytes(sched_cap);
+    const size_t stride = (p->dyn_bytes(sched_cap) + 255) & ~size_t(255);
+    const size_t bytes = stride * size_t(p->n_tables);
     hipError_t e = dev_alloc(&d, bytes);
     if (e != hipSuccess) return from_hip(e);
     e = hipHostMalloc(&h, bytes, hipHostMallocDefault);
@@ -412,14 +422,17 @@ vbw_status alloc_dyn(vbw_plan_s *p, size_t sched_cap) {
     }
     if (p->d_dyn) (void)hipFree(p->d_dyn);        // hipFree waits for queued work
     if (p->h_stage) {
-        if (p->upload_pending) (void)hipEventSynchronize(p->upload_evt);
+        for (int i = 0; i < 2; ++i)
+            if (p->pending[i]) (void)hipEventSynchronize(p->upload_evt[i]);
         (void)hipHostFree(p->h_stage);
     }
     p->d_dyn = static_cast<unsigned char *>(d);
     p->h_stage = static_cast<unsigned char *>(h);
     p->stage_bytes = bytes;
+    p->dyn_stride = stride;
     p->dyn_cap_sched = sched_cap;
-    p->upload_pending = false;
+    p->pending[0] = p->pending[1] = false;
+    p->cur = 0;
     p->dyn_valid = false;
     // the captured graph holds the old table addresses
     if (p->graph_exec) {
@@ -478,7 +491,9 @@ vbw_status setup_device(vbw_plan_s *p) {
         (e = hipMemcpy(p->d_wg_begin, p->wg_begin.data(), p->wg_begin.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return from_hip(e);
-    if ((e = hipEventCreateWithFlags(&p->upload_evt, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
+    p->n_tables = (p->flags & VBW_GRAPH) ? 1 : 2;
+    for (auto &ev : p->upload_evt)
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
     if ((e = hipEventCreateWithFlags(&p->done_evt, hipEventDisableTiming)) != hipSuccess) return from_hip(e);
     vbw_status st = alloc_dyn(p, std::max<size_t>(p->sched_entries(), 2 * p->ch.size()));
     if (st != VBW_OK) return st;
@@ -542,12 +557,13 @@ vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipSt
         vbw_status st = alloc_dyn(p, std::max(need, 2 * p->dyn_cap_sched));
         if (st != VBW_OK) return st;
     }
-    if (p->upload_pending) {
-        hipError_t e = hipEventSynchronize(p->upload_evt);
+    const int next = (p->cur + 1) % p->n_tables;
+    if (p->pending[next]) {     // its staging buffer may still be in an earlier copy
+        hipError_t e = hipEventSynchronize(p->upload_evt[next]);
         if (e != hipSuccess) return from_hip(e);
-        p->upload_pending = false;
+        p->pending[next] = false;
     }
-    unsigned char *h = p->h_stage;
+    unsigned char *h = p->h_stage + size_t(next) * p->dyn_stride;
     ChannelDev *hc = reinterpret_cast<ChannelDev *>(h);
     const void **hx = reinterpret_cast<const void **>(h + nch * sizeof(ChannelDev));
     void **hy = reinterpret_cast<void **>(h + nch * (sizeof(ChannelDev) + sizeof(void *)));
@@ -575,10 +591,11 @@ vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipSt
         hy[c] = y[c];
     }
     const size_t bytes = p->dyn_bytes(size_t(so));
-    hipError_t e = hipMemcpyAsync(p->d_dyn, h, bytes, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(p->d_dyn + size_t(next) * p->dyn_stride, h, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return from_hip(e);
-    if ((e = hipEventRecord(p->upload_evt, s)) != hipSuccess) return from_hip(e);
-    p->upload_pending = true;
+    if ((e = hipEventRecord(p->upload_evt[next], s)) != hipSuccess) return from_hip(e);
+    p->pending[next] = true;
+    p->cur = next;
     p->dyn_valid = true;
     p->sched_dirty = false;
     p->last_x.assign(x, x + nch);
@@ -590,10 +607,11 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
     const size_t nch = p->ch.size();
     vbw::LaunchArgs a;
     a.items = p->d_items;
-    a.ch = reinterpret_cast<const ChannelDev *>(p->d_dyn);
-    a.x = reinterpret_cast<const void *const *>(p->d_dyn + nch * sizeof(ChannelDev));
-    a.y = reinterpret_cast<void *const *>(p->d_dyn + nch * (sizeof(ChannelDev) + sizeof(void *)));
-    a.sched = reinterpret_cast<const SchedDev *>(p->d_dyn + nch * (sizeof(ChannelDev) + 2 * sizeof(void *)));
+    const unsigned char *t = p->d_dyn + size_t(p->cur) * p->dyn_stride;
+    a.ch = reinterpret_cast<const ChannelDev *>(t);
+    a.x = reinterpret_cast<const void *const *>(t + nch * sizeof(ChannelDev));
+    a.y = reinterpret_cast<void *const *>(t + nch * (sizeof(ChannelDev) + sizeof(void *)));
+    a.sched = reinterpret_cast<const SchedDev *>(t + nch * (sizeof(ChannelDev) + 2 * sizeof(void *)));
     a.v = p->d_v;
     a.tw = p->d_tw;
     a.n_items = int32_t(p->work.size());
