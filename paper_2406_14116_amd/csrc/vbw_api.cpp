@@ -702,7 +702,11 @@ vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out) {
     }
     if (!(desc->flags & VBW_HOST_ONLY)) {
         g_alloc_count = 0;
-        st = setup_device(p);
+        try {
+            st = setup_device(p);
+        } catch (const std::bad_alloc &) {   // host tables of the planner
+            st = VBW_ENOMEM;
+        }
         if (st != VBW_OK) {
             free_device(p);
             delete p;
@@ -733,7 +737,17 @@ vbw_status vbw_set_bandwidth(vbw_plan_t p, int32_t channel, int32_t k1, int64_t 
     return VBW_OK;
 }
 
+static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream);
+
 vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *stream) {
+    try {
+        return filter_impl(p, x, y, stream);
+    } catch (const std::bad_alloc &) {   // host copies of the pointer arrays
+        return VBW_ENOMEM;
+    }
+}
+
+static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream) {
     if (!p || !x || !y) return VBW_EINVAL;
     if (p->host_only) return VBW_EUNSUPPORTED;
     if (!ranges_ok(p, x, y)) return VBW_EINVAL;

@@ -28,6 +28,21 @@ def test_library_exports_every_declared_function():
         assert hasattr(L, name), name
 
 
+def test_library_exports_only_declared_c_functions():
+    """The C symbols the library exports are exactly those the header declares
+    (everything else has C++ or internal linkage)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm missing")
+    out = subprocess.run([nm, "-D", "--defined-only", vbw.LIB_PATH], check=True, capture_output=True,
+                         text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines()
+                if len(line.split()) == 3 and line.split()[1] == "T" and not line.split()[-1].startswith("_")}
+    assert exported == set(vbw.header_functions())
+
+
 def test_strerror_codes():
     for code in (0, -1, -2, -3, -4, -5):
         assert vbw.strerror(code) and vbw.strerror(code) != "unknown status"
