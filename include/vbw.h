@@ -156,7 +156,11 @@ vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
  * be queued (or replayed from a graph) without host synchronisation.
  * With VBW_AUTOTUNE the first call also times every launch variant on these
  * buffers (blocking; the outputs are the filter's outputs all the same) and
- * keeps the fastest for the plan's lifetime.  With VBW_GRAPH and a non-null
+ * keeps the fastest for the plan's lifetime.  When the environment variable
+ * VBW_TUNE_CACHE names a file, the choice is appended to it as one
+ * "key variant" line (key: device, storage, engine, kernel flags and the
+ * block count per N, rounded to a power of two), and a plan whose key is in
+ * the file takes that variant at creation without timing.  With VBW_GRAPH and a non-null
  * stream the launches are captured once into a HIP graph and replayed.
  * Errors: VBW_EINVAL (NULL plan or arrays, NULL pointer for a channel with
  * len > 0, an output range overlapping any other input or output range);

@@ -12,7 +12,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
 #include <new>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -446,6 +448,9 @@ vbw_status alloc_dyn(vbw_plan_s *p, size_t sched_cap) {
     return VBW_OK;
 }
 
+std::string tune_key(const vbw_plan_s *p);
+int tune_cache_lookup(const std::string &key);
+
 vbw_status setup_device(vbw_plan_s *p) {
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) return from_hip(e);
@@ -478,6 +483,13 @@ vbw_status setup_device(vbw_plan_s *p) {
     if (const char *v = std::getenv("VBW_VARIANT")) {
         const int k = std::atoi(v);
         if (*v && k >= 0 && size_t(k) < p->variants.size()) {
+            p->variant = k;
+            p->tuned = true;
+        }
+    }
+    if ((p->flags & VBW_AUTOTUNE) && !p->tuned) {
+        const int k = tune_cache_lookup(tune_key(p));
+        if (k >= 0 && size_t(k) < p->variants.size()) {
             p->variant = k;
             p->tuned = true;
         }
@@ -644,6 +656,50 @@ hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant, bool advance 
 
 // Time every launch variant on the caller's buffers (filtering is idempotent:
 // each run rewrites the same outputs) and keep the fastest.  Blocking, once.
+// Tuning cache: with VBW_TUNE_CACHE=<file>, the autotuner's choice is kept
+// as one "key variant" line per plan shape and reused by later plans (and
+// processes) of the same shape instead of timing again.  The key holds the
+// device architecture and CU count, storage, engine, the flags that change
+// the kernels, and per N the log2 of the block count.
+std::string tune_key(const vbw_plan_s *p) {
+    hipDeviceProp_t prop;
+    std::string key = "vbw1";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+        key += ":";
+        for (const char *c = prop.gcnArchName; *c && *c != ':'; ++c) key += *c;
+        key += ":" + std::to_string(prop.multiProcessorCount);
+    }
+    key += ":d" + std::to_string(p->dtype) + ":e" + std::to_string(p->engine) + ":f" +
+           std::to_string(p->flags & (VBW_NO_PRUNE | VBW_F32_OUT | VBW_STREAM));
+    int64_t blocks[vbw::kMaxLog2N + 1] = {};
+    for (const auto &it : p->items) blocks[it.log2n] += it.n_blocks;
+    for (int lg = 0; lg <= vbw::kMaxLog2N; ++lg)
+        if (blocks[lg]) key += ":n" + std::to_string(lg) + "b" + std::to_string(int(std::log2(double(blocks[lg]))));
+    return key;
+}
+
+int tune_cache_lookup(const std::string &key) {
+    const char *path = std::getenv("VBW_TUNE_CACHE");
+    if (!path || !*path) return -1;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return -1;
+    char k[1024];
+    int v = -1, found = -1;
+    while (std::fscanf(f, "%1023s %d", k, &v) == 2)
+        if (key == k) found = v;      // the last line for a key wins
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_store(const std::string &key, int variant) {
+    const char *path = std::getenv("VBW_TUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s %d\n", key.c_str(), variant);
+        std::fclose(f);
+    }
+}
+
 vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
     if (p->variants.size() < 2) {
         p->tuned = true;
@@ -672,6 +728,10 @@ vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
     if (e != hipSuccess) return from_hip(e);
     p->variant = best_v;
     p->tuned = true;
+    try {
+        tune_cache_store(tune_key(p), best_v);
+    } catch (const std::bad_alloc &) {
+    }
     return VBW_OK;
 }
 

@@ -688,3 +688,38 @@ def test_real_input_config2_full_size_sampled():
         assert e <= FP32_DB, (ci, e)
     say("real config 2: worst dB", worst)
     plan.close()
+
+
+def test_tuning_cache_is_written_and_read(monkeypatch, tmp_path):
+    """VBW_TUNE_CACHE: the autotuner appends its choice for the plan's shape;
+    a later plan of that shape takes the variant the file names (here edited
+    to a different one) without timing again, and still filters correctly."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("VBW_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(12)
+    specs = [(256, 192, 8, 20, 60000, (256, 8)), (1024, 768, 16, 100, 200000, (1024, 16))]
+    v_sets = v_for({s[5] for s in specs})
+    chans, pool = channels_from(specs, v_sets)
+    xs = [torch.from_numpy(crandn(rng, s[4])).cuda() for s in specs]
+    ref = [ols.channel_hfso(x.cpu().numpy().astype(np.complex128), s[0], s[1], v_sets[s[5]], [(0, s[3])])
+           for x, s in zip(xs, specs)]
+    p1 = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE)
+    n_var = p1.query(vbw.Q_N_VARIANTS)
+    ys = [torch.empty_like(x) for x in xs]
+    run_plan(p1, xs, ys)
+    v1 = p1.query(vbw.Q_VARIANT)
+    p1.close()
+    lines = cache.read_text().split("\n")
+    lines = [ln for ln in lines if ln.strip()]
+    assert len(lines) == 1 and lines[0].split()[1] == str(v1)
+    other = (v1 + 1) % n_var
+    cache.write_text(f"{lines[0].split()[0]} {other}\n")
+    p2 = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE)
+    assert p2.query(vbw.Q_VARIANT) == other
+    ys = [torch.empty_like(x) for x in xs]
+    run_plan(p2, xs, ys)
+    assert p2.query(vbw.Q_VARIANT) == other
+    assert len([ln for ln in cache.read_text().split("\n") if ln.strip()]) == 1   # no second timing
+    for y, r in zip(ys, ref):
+        assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
+    p2.close()
