@@ -7,6 +7,7 @@
 // transition values V(r) so that a bandwidth change is an integer update with
 // no arithmetic (Sec. III-D).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -35,6 +36,15 @@ vbw_status from_hip(hipError_t e) {
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return VBW_ENOMEM;
     return VBW_EDEVICE;
 }
+
+// ROCTx range around a C entry point: plan set-up, filter calls and the
+// autotuner show up by name in a marker trace (rocprofv3 --marker-trace).
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 // Test hook: VBW_FAIL_DEVICE_ALLOC=k makes the k-th device allocation made by
 // one vbw_plan call fail (1-based), to exercise the ENOMEM path without leaks.
@@ -701,6 +711,7 @@ void tune_cache_store(const std::string &key, int variant) {
 }
 
 vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
+    const Range range("vbw_autotune");
     if (p->variants.size() < 2) {
         p->tuned = true;
         return VBW_OK;
@@ -740,6 +751,7 @@ vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
 extern "C" {
 
 vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out) {
+    const Range range("vbw_plan");
     if (!out) return VBW_EINVAL;
     *out = nullptr;
     vbw_status st = validate_desc(desc);
@@ -800,6 +812,7 @@ vbw_status vbw_set_bandwidth(vbw_plan_t p, int32_t channel, int32_t k1, int64_t 
 static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream);
 
 vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *stream) {
+    const Range range("vbw_filter");
     try {
         return filter_impl(p, x, y, stream);
     } catch (const std::bad_alloc &) {   // host copies of the pointer arrays

@@ -31,7 +31,7 @@ def test_host_plan_logic_under_sanitizers(tmp_path):
                 "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2406_14116_amd", "csrc"),
                 os.path.join(ROOT, "tests", "sanitize", "host_plan_check.cpp"),
                 os.path.join(ROOT, "paper_2406_14116_amd", "csrc", "vbw_api.cpp"),
-                "-L", lib, "-Wl,-rpath," + lib, "-lamdhip64", "-o", exe], exe)
+                "-L", lib, "-Wl,-rpath," + lib, "-lamdhip64", "-lrocprofiler-sdk-roctx", "-o", exe], exe)
     assert "0 failures" in out
 
 
