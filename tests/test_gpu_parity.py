@@ -723,3 +723,60 @@ def test_tuning_cache_is_written_and_read(monkeypatch, tmp_path):
     for y, r in zip(ys, ref):
         assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
     p2.close()
+
+
+@pytest.mark.parametrize("seed", [101, 202, 303])
+def test_random_plans_against_oracle(seed):
+    """Seeded random plans: mixed N and hops (even N - hop), lengths from 0 to
+    a few dozen blocks, band schedules, complex or real input, pruned or not;
+    every channel against the oracle."""
+    rng = np.random.default_rng(seed)
+    dtype = ["c64", "r32", "c64"][seed % 3]
+    flags = int(rng.choice([0, vbw.NO_PRUNE, vbw.GRAPH]))
+    specs, sched = [], {}
+    for ci in range(16):
+        n = 1 << int(rng.integers(4, 13))
+        hop = n - 2 * int(rng.integers(1, n // 2))
+        lv = int(rng.integers(0, min(12, n // 2 - 1)))
+        k1 = int(rng.integers(1, n // 2 - lv)) if lv else int(rng.integers(1, n // 2))
+        nb = int(rng.integers(0, 24 if n >= 1024 else 60))
+        length = max(0, nb * hop - int(rng.integers(0, hop)))
+        specs.append((n, hop, lv, k1, length, (n, lv)))
+        if nb > 2 and rng.random() < 0.6:
+            frm = int(rng.integers(1, nb))
+            k1b = int(rng.integers(1, n // 2 - lv)) if lv else int(rng.integers(1, n // 2))
+            sched[ci] = [(frm, k1b)]
+    v_sets = v_for({s[5] for s in specs})
+    if dtype == "r32":
+        xs = [rrandn(rng, s[4]) for s in specs]
+        ys = filter_real(specs, v_sets, xs, schedules=sched, flags=flags)
+    else:
+        xs = [crandn(rng, s[4]) for s in specs]
+        chans, pool = channels_from(specs, v_sets)
+        plan = vbw.Plan(chans, pool, flags=flags)
+        for ch, entries in sched.items():
+            for frm, k1 in entries:
+                plan.set_bandwidth(ch, k1, frm)
+        xd = [torch.from_numpy(x).cuda() for x in xs]
+        yd = [torch.full((len(x),), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda") for x in xs]
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            plan.filter(xd, yd, stream)
+            plan.filter(xd, yd, stream)      # a graph plan replays on the second call
+        stream.synchronize()
+        ys = [y.cpu().numpy().astype(np.complex128) for y in yd]
+        plan.close()
+    worst = -np.inf
+    for ci, (spec, x, y) in enumerate(zip(specs, xs, ys)):
+        if spec[4] == 0:
+            continue
+        entries = [(0, spec[3])] + sched.get(ci, [])
+        ref = oracle_real(spec, v_sets, x, entries) if dtype == "r32" else oracle_full(spec, v_sets, x, entries)
+        assert np.all(np.isfinite(y)), spec
+        e = ols.error_db(y, ref)
+        if spec[4] < 2 * spec[1] or spec[4] < (spec[0] - spec[1]) // 2 + spec[1]:
+            e = 10 * np.log10(np.sum(np.abs(y - ref) ** 2) / np.sum(np.abs(x) ** 2) + 1e-300)
+        worst = max(worst, e)
+        assert e <= FP32_DB, (spec, sched.get(ci), e)
+    say("random plans", seed, dtype, flags, "worst dB", worst)
