@@ -780,3 +780,28 @@ def test_random_plans_against_oracle(seed):
         worst = max(worst, e)
         assert e <= FP32_DB, (spec, sched.get(ci), e)
     say("random plans", seed, dtype, flags, "worst dB", worst)
+
+
+def test_plain_c_consumer(tmp_path):
+    """The C ABI used from C alone (no Python binding, no PyTorch): a program
+    built with gcc against include/vbw.h and libvbw.so filters one channel
+    with a band change and checks it against the oracle's C code."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if gcc is None:
+        pytest.skip("gcc missing")
+    exe = str(tmp_path / "vbw_c_consumer")
+    libdir = os.path.dirname(vbw.LIB_PATH)
+    subprocess.run([gcc, "-std=c11", "-O2", "-fopenmp", "-D__HIP_PLATFORM_AMD__",
+                    "-I", os.path.join(root, "include"), "-I", os.path.join(rocm, "include"),
+                    os.path.join(root, "tests", "c_consumer", "vbw_c_consumer.c"),
+                    os.path.join(root, "oracle", "ols_oracle.c"),
+                    "-L", libdir, "-Wl,-rpath," + libdir, "-l:" + os.path.basename(vbw.LIB_PATH),
+                    "-L", os.path.join(rocm, "lib"), "-Wl,-rpath," + os.path.join(rocm, "lib"), "-lamdhip64",
+                    "-lm", "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    say(r.stdout.strip())
+    assert r.returncode == 0, r.stdout + r.stderr
