@@ -185,6 +185,21 @@ class Plan:
         import torch
         if len(xs) != self.n_channels or len(ys) != self.n_channels:
             raise ValueError("one input and one output tensor per channel")
+        # the kernels address len samples of the plan's storage from each
+        # pointer: check element types and sizes before handing pointers over
+        in_types = {"c64": (torch.complex64,), "f16": (torch.float16,), "bf16": (torch.bfloat16,),
+                    "r32": (torch.float32,)}[self.dtype]
+        f32_out = bool(self.flags & F32_OUT) and self.dtype in ("f16", "bf16")
+        out_types = (torch.complex64, torch.float32) if f32_out else in_types
+        in_bytes = {"c64": 8, "f16": 4, "bf16": 4, "r32": 4}[self.dtype]
+        out_bytes = 8 if f32_out else in_bytes
+        for i, (x, y) in enumerate(zip(xs, ys)):
+            if x.dtype not in in_types or y.dtype not in out_types:
+                raise ValueError(f"channel {i}: input must be {in_types}, output {out_types} for {self.dtype} "
+                                 f"storage (got {x.dtype}, {y.dtype})")
+            if x.numel() * x.element_size() < self.lengths[i] * in_bytes or \
+                    y.numel() * y.element_size() < self.lengths[i] * out_bytes:
+                raise ValueError(f"channel {i}: tensors hold fewer than len = {self.lengths[i]} samples")
         for t in list(xs) + list(ys):
             if not t.is_cuda or not t.is_contiguous():
                 raise ValueError("tensors must be contiguous and on the GPU")

@@ -227,3 +227,31 @@ def test_stream_plan_validation():
         plain.stream_reset(0)
     assert e.value.status == vbw.VBW_EINVAL
     plain.close()
+
+
+def test_binding_checks_tensor_types_and_sizes():
+    """The binding refuses tensors whose element type does not match the
+    plan's storage or that hold fewer than len samples (the kernels would read
+    or write past them), before any pointer reaches the library."""
+    torch = pytest.importorskip("torch")
+    p = host_plan([chan(length=1000)])
+    ok_x = torch.zeros(1000, dtype=torch.complex64)
+    with pytest.raises(ValueError, match="fewer than"):
+        p.filter([torch.zeros(999, dtype=torch.complex64)], [ok_x])
+    with pytest.raises(ValueError, match="fewer than"):
+        p.filter([ok_x], [torch.zeros(10, dtype=torch.complex64)])
+    with pytest.raises(ValueError, match="input must be"):
+        p.filter([torch.zeros((1000, 2), dtype=torch.float16)], [ok_x])
+    with pytest.raises(ValueError, match="on the GPU"):      # right type and size, but host memory
+        p.filter([ok_x], [torch.zeros(1000, dtype=torch.complex64)])
+    p.close()
+    p = host_plan([chan(length=1000)], dtype="f16", flags=vbw.F32_OUT)
+    with pytest.raises(ValueError, match="on the GPU"):
+        p.filter([torch.zeros((1000, 2), dtype=torch.float16)], [torch.zeros(1000, dtype=torch.complex64)])
+    with pytest.raises(ValueError, match="fewer than"):
+        p.filter([torch.zeros((1000, 2), dtype=torch.float16)], [torch.zeros((1000, 1), dtype=torch.float32)])
+    p.close()
+    p = host_plan([chan(length=1000)], dtype="r32")
+    with pytest.raises(ValueError, match="input must be"):
+        p.filter([torch.zeros(1000, dtype=torch.complex64)], [torch.zeros(1000, dtype=torch.float32)])
+    p.close()
