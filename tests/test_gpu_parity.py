@@ -805,3 +805,47 @@ def test_plain_c_consumer(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     say(r.stdout.strip())
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+
+def test_maximum_sizes():
+    """Large sizes: one channel of 1.6e9 complex64 samples (12.9 GB in, 12.9 GB
+    out; byte offsets past 2^31 and 2^32, spans cut at the 2^26-sample limit),
+    checked block by block around those offsets and at both ends; and N = 4096
+    with the widest transition band (L_V = 2047, k1 = 1, so k2 = N/2 - 1)."""
+    n, hop, lv, k1 = 1024, 768, 16, 100
+    length = 3 * (1 << 29) + 12345
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    x = torch.randn(length, dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    v = v_for({(n, lv)})[(n, lv)]
+    p = vbw.Plan([dict(n=n, hop=hop, lv=lv, v_offset=0, k1=k1, len=length)], v)
+    run_plan(p, [x], [y])
+    p.close()
+    nb = -(-length // hop)
+    marks = [0, (1 << 26) // hop, (1 << 28) // hop, (1 << 29) // hop, nb // 2, nb - 1]
+    blocks = sorted({b + d for b in marks for d in (-1, 0, 1) if 0 <= b + d < nb})
+    lead = -(-(n - hop) // hop)          # blocks whose samples reach back into block b
+    worst = -np.inf
+    for b in blocks:
+        b0 = min(b, lead)                # block b of the channel is block b0 of x[start:]
+        start = (b - b0) * hop
+        hi = min(length, (b + 1) * hop)
+        xloc = x[start:hi].cpu().numpy()
+        ref = ols.blocks_hfso(xloc, n, hop, v, [(0, k1)], blocks=[b0])[0][: hi - b * hop]
+        got = y[b * hop:hi].cpu().numpy()
+        e = ols.error_db(got, ref)
+        worst = max(worst, e)
+        assert e <= FP32_DB, (b, e)
+    say("1.6e9-sample channel, %d blocks checked: worst dB" % len(blocks), worst)
+    del x, y
+    torch.cuda.empty_cache()
+    n, hop, lv, k1 = 4096, 3072, 2047, 1
+    v = wl.draw_v(7, 99, n, lv)
+    rng = np.random.default_rng(21)
+    xs = crandn(rng, 9 * hop + 11)
+    ys = filter_full([(n, hop, lv, k1, len(xs), (n, lv))], {(n, lv): v}, [xs])
+    e = ols.error_db(ys[0], ols.channel_hfso(xs, n, hop, v, [(0, k1)]))
+    say("N = 4096, L_V = 2047, k1 = 1: dB", e)
+    assert e <= FP32_DB
