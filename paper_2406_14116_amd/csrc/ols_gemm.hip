@@ -179,6 +179,7 @@ __device__ __forceinline__ void gemm_block(const GemmConst &K, __amdgpu_buffer_r
     const int g = lane >> 4, c = lane & 15;
     // S1 operand A = x^T: lane (g, n2 = c) holds x[n1 = 4g + j][n2], j < 4
     h4 ar, ai;
+    __builtin_amdgcn_s_setprio(1);   // loads out ahead of other waves' arithmetic
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int i = base + 16 * (4 * g + j) + c;
@@ -188,6 +189,7 @@ __device__ __forceinline__ void gemm_block(const GemmConst &K, __amdgpu_buffer_r
         ar[j] = re;
         ai[j] = im;
     }
+    __builtin_amdgcn_s_setprio(0);
     // S1: D1[n2][k1] = sum_n1 x^T[n2][n1] W[n1][k1]
     CF4 d;
     {
