@@ -40,9 +40,11 @@
  * failures to VBW_ENOMEM.
  *
  * Threading: one plan is used by one host thread at a time; distinct plans are
- * independent.  All vbw_filter calls on one plan must be ordered (same stream,
- * or the caller synchronizes between streams): the plan's device tables are
- * updated stream-ordered by the next vbw_filter call.
+ * independent.  The device work of the calls on one plan runs in call order:
+ * a vbw_filter or vbw_stream_reset on another stream than the plan's previous
+ * call first makes that stream wait (on the device, no host synchronisation)
+ * for the previous call's work, since it may rewrite the per-call tables and
+ * the stream state that work reads.
  */
 #ifndef VBW_H
 #define VBW_H

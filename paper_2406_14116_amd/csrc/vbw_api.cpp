@@ -172,7 +172,9 @@ struct vbw_plan_s {
     size_t stage_bytes = 0;
     hipEvent_t upload_evt[2] = {nullptr, nullptr};
     bool pending[2] = {false, false};
-    hipEvent_t done_evt = nullptr;
+    hipEvent_t done_evt = nullptr;    // end of the plan's last queued call
+    bool done_recorded = false;
+    hipStream_t last_stream = nullptr;
     bool dyn_valid = false;
     bool sched_dirty = true;
     std::vector<const void *> last_x;
@@ -811,6 +813,23 @@ vbw_status vbw_set_bandwidth(vbw_plan_t p, int32_t channel, int32_t k1, int64_t 
 
 static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream);
 
+// Calls on one plan run in call order: a call on another stream than the
+// plan's last call first waits, on the device, for that call's work (it may
+// still read the per-call table or the stream state this call rewrites).
+static hipError_t order_after_last(vbw_plan_t p, hipStream_t s) {
+    if (!p->done_recorded || s == p->last_stream) return hipSuccess;
+    return hipStreamWaitEvent(s, p->done_evt, 0);
+}
+
+static hipError_t record_done(vbw_plan_t p, hipStream_t s) {
+    const hipError_t e = hipEventRecord(p->done_evt, s);
+    if (e == hipSuccess) {
+        p->done_recorded = true;
+        p->last_stream = s;
+    }
+    return e;
+}
+
 vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *stream) {
     const Range range("vbw_filter");
     try {
@@ -830,11 +849,11 @@ static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y
     if (e != hipSuccess) return from_hip(e);
     if (prev != p->device && (e = hipSetDevice(p->device)) != hipSuccess) return from_hip(e);
 
-    vbw_status st = VBW_OK;
+    vbw_status st = from_hip(order_after_last(p, s));
     const size_t nch = p->ch.size();
     const bool ptrs_same = p->dyn_valid && std::equal(x, x + nch, p->last_x.begin()) &&
                            std::equal(y, y + nch, p->last_y.begin());
-    if (!ptrs_same || p->sched_dirty) st = upload_dyn(p, x, y, s);
+    if (st == VBW_OK && (!ptrs_same || p->sched_dirty)) st = upload_dyn(p, x, y, s);
 
     if (st == VBW_OK && !p->items.empty() && (p->flags & VBW_AUTOTUNE) && !p->tuned) st = autotune(p, s);
     if (st == VBW_OK && !p->items.empty()) {
@@ -854,7 +873,7 @@ static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y
             st = from_hip(launch(p, s, p->variant));
         }
     }
-    if (st == VBW_OK) st = from_hip(hipEventRecord(p->done_evt, s));
+    if (st == VBW_OK) st = from_hip(record_done(p, s));
     if (prev != p->device) (void)hipSetDevice(prev);
     return st;
 }
@@ -867,8 +886,9 @@ vbw_status vbw_stream_reset(vbw_plan_t p, void *stream) {
     if (e != hipSuccess) return from_hip(e);
     if (prev != p->device && (e = hipSetDevice(p->device)) != hipSuccess) return from_hip(e);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    e = vbw::launch_stream_reset(p->d_hist, p->hist_bytes, p->d_block0, int(p->ch.size()), s);
-    if (e == hipSuccess) e = hipEventRecord(p->done_evt, s);
+    e = order_after_last(p, s);
+    if (e == hipSuccess) e = vbw::launch_stream_reset(p->d_hist, p->hist_bytes, p->d_block0, int(p->ch.size()), s);
+    if (e == hipSuccess) e = record_done(p, s);
     if (prev != p->device) (void)hipSetDevice(prev);
     return from_hip(e);
 }

@@ -535,6 +535,46 @@ def test_stream_chunks_equal_one_shot(storage, flags):
     ps.close()
 
 
+def test_calls_on_alternating_streams_run_in_call_order():
+    """Consecutive calls of one streaming plan on two streams, with new buffers
+    on every call and no host synchronisation in between: each call waits, on
+    the device, for the previous one (whose history, block counters and
+    per-call table it rewrites), so the chunks come out bit for bit as one
+    call over the whole input.  The first stream is kept busy beforehand, so
+    that without the wait the second stream's call would run first."""
+    specs = STREAM_SPECS[:3]
+    calls = 6
+    rng = np.random.default_rng(23)
+    v_sets = v_for({(s[0], s[2]) for s in specs})
+    chunk = [s[4] * s[1] for s in specs]
+    total = [c * calls for c in chunk]
+    mk = lambda lens: channels_from([(s[0], s[1], s[2], s[3], L, (s[0], s[2])) for s, L in zip(specs, lens)],
+                                    v_sets)
+    xs_full = [torch.from_numpy(crandn(rng, L)).cuda() for L in total]
+    ys_one = [torch.empty_like(x) for x in xs_full]
+    x_parts = [[x[i * c:(i + 1) * c].clone() for x, c in zip(xs_full, chunk)] for i in range(calls)]
+    y_parts = [[torch.full_like(xp, complex(np.nan, np.nan)) for xp in xp_i] for xp_i in x_parts]
+    chans1, pool = mk(total)
+    p1 = vbw.Plan(chans1, pool, flags=vbw.NO_PRUNE)
+    chans_s, _ = mk(chunk)
+    ps = vbw.Plan(chans_s, pool, flags=vbw.NO_PRUNE | vbw.STREAM)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    busy = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(streams[0]):
+        for _ in range(8):
+            busy = (busy @ busy) * (1.0 / 64.0)
+    for i in range(calls):
+        ps.filter(x_parts[i], y_parts[i], streams[i % 2])
+    p1.filter(xs_full, ys_one, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for ci, s in enumerate(specs):
+        got = torch.cat([y_parts[i][ci] for i in range(calls)])
+        assert torch.equal(got.cpu().view(torch.int64), ys_one[ci].cpu().view(torch.int64)), s
+    p1.close()
+    ps.close()
+
+
 def test_designed_filter_meets_paper_spec_on_gpu():
     """The paper's example (Sec. IV): V from the minimax design for L = 33,
     N = 128, M = 96, b_N in [48, 55]; the GPU path filters complex
