@@ -18,6 +18,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+# per-source flags: the matrix-core kernel keeps its MFMA accumulators in
+# ordinary VGPRs (no accumulator-register reads after every product)
+SOURCE_FLAGS = {"ols_gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose: bool = False, extra=()) -> str:
@@ -25,7 +28,7 @@ def build(verbose: bool = False, extra=()) -> str:
     objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        cmds.append([HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        cmds.append([HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                      "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
 

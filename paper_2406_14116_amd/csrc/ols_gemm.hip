@@ -29,6 +29,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "vbw_internal.h"
 
 namespace vbw {
@@ -170,26 +172,37 @@ template <Storage S, bool F32OUT> __device__ __forceinline__ void gstore(__amdgp
     }
 }
 
-// One OLS block of N = 256 by one wave.  base = sample index of the segment
-// start relative to the input resource (may be negative: zero history).
+// The samples of one block: base = sample index of the segment start relative
+// to the input resource (may be negative: zero history); lane (g, c) reads
+// x[n1 = 4g + j][n2 = c], j < 4.  valid = false reads past the resource's end
+// (zeros, no memory access).
+__device__ __forceinline__ void gemm_load(__amdgpu_buffer_rsrc_t xr, int base, int lane, bool valid,
+                                          uint32_t (&u)[4]) {
+    const int g = lane >> 4, c = lane & 15;
+    __builtin_amdgcn_s_setprio(1);   // loads out ahead of other waves' arithmetic
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = base + 16 * (4 * g + j) + c;
+        u[j] = __builtin_amdgcn_raw_buffer_load_b32(xr, valid && i >= 0 ? i * 4 : kOutOfRange, 0, kNT);
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
+// One OLS block of N = 256 by one wave, its samples already loaded into u.
 template <Storage S, bool F32OUT>
-__device__ __forceinline__ void gemm_block(const GemmConst &K, __amdgpu_buffer_rsrc_t xr, int base,
+__device__ __forceinline__ void gemm_block(const GemmConst &K, const uint32_t (&u)[4],
                                            __amdgpu_buffer_rsrc_t yr, int obase, int hop, int k1, int lv,
                                            const float *vl, int lane) {
     const int g = lane >> 4, c = lane & 15;
     // S1 operand A = x^T: lane (g, n2 = c) holds x[n1 = 4g + j][n2], j < 4
     h4 ar, ai;
-    __builtin_amdgcn_s_setprio(1);   // loads out ahead of other waves' arithmetic
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int i = base + 16 * (4 * g + j) + c;
-        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(xr, i >= 0 ? i * 4 : kOutOfRange, 0, kNT);
         _Float16 re, im;
-        GIo<S>::unpack(u, re, im);
+        GIo<S>::unpack(u[j], re, im);
         ar[j] = re;
         ai[j] = im;
     }
-    __builtin_amdgcn_s_setprio(0);
     // S1: D1[n2][k1] = sum_n1 x^T[n2][n1] W[n1][k1]
     CF4 d;
     {
@@ -296,16 +309,26 @@ __global__ __launch_bounds__(kThreads) void ols_gemm_kernel(const LaunchArgs A) 
         constexpr int EO = F32OUT ? 8 : 4;
         const int64_t ob = int64_t(it.first_block) * hop;
         const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, it.channel)) + ob * EO, (cd.len - ob) * EO);
-        for (int q = 0; q < kGemmHop4; ++q) {
-            const int b = kGemmHop4 * wave + q;              // block within the item
-            if (b >= it.n_blocks) break;
+        // the next block's samples are loaded while this one is filtered; the
+        // load is issued on every step (past the end after the last block) so
+        // that the wait before the products has a fixed count
+        const int first = kGemmHop4 * wave;                  // this wave's first block of the item
+        const int nb = std::min(kGemmHop4, it.n_blocks - first);
+        const int base0 = int(seg0 - clip);
+        uint32_t u[4], un[4];
+        if (nb > 0) gemm_load(xr, base0 + first * hop, lane, true, u);
+        for (int q = 0; q < nb; ++q) {
+            const int b = first + q;                         // block within the item
+            gemm_load(xr, base0 + (b + 1) * hop, lane, q + 1 < nb, un);
             const int64_t m = int64_t(it.first_block) + b;
             int k1 = ld_uniform(A.sched, cd.sched_begin).k1;
             for (int e = 1; e < cd.sched_count; ++e) {
                 const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
                 if (sd.from_block <= m) k1 = sd.k1;
             }
-            gemm_block<S, F32OUT>(K, xr, int(seg0 - clip) + b * hop, yr, b * hop, hop, k1, cd.lv, vlds, lane);
+            gemm_block<S, F32OUT>(K, u, yr, b * hop, hop, k1, cd.lv, vlds, lane);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u[j] = un[j];
         }
     }
 }

@@ -459,6 +459,52 @@ def test_16bit_store_is_nearest_even_of_float32_result(storage, engine):
     p32.close()
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_gemm_engine_edge_shapes_every_block(storage, monkeypatch):
+    """The matrix-core engine (N = 256) on short and ragged channels, hops from
+    2 to N - 2, the all-pass and the widest bands, band switches inside and
+    between work items, and both of its launch variants: every output sample
+    against the oracle on the stored 16-bit input (float32 output, so that
+    only the engine's arithmetic is measured)."""
+    n = 256
+    specs = [  # (hop, lv, k1, len)
+        (192, 8, 24, 20000), (192, 8, 24, 1), (192, 8, 24, 191), (192, 8, 24, 193),
+        (254, 8, 100, 4099), (2, 3, 5, 1000), (128, 127, 1, 3000), (64, 0, 129, 2500),
+        (192, 1, 127, 7777), (100, 16, 40, 0), (192, 8, 24, 16 * 192 * 3 + 5)]
+    sched = {0: [(5, 60), (17, 10), (40, 100)], 4: [(3, 20)], 10: [(16, 50), (32, 24)]}
+    v_sets = {(n, lv): wl.draw_v(7, 99, n, lv) for (_, lv, _, _) in specs}
+    chans, pool = channels_from([(n, hop, lv, k1, L, (n, lv)) for (hop, lv, k1, L) in specs], v_sets)
+    rng = np.random.default_rng(31)
+    xs = [harness.host_to_storage(crandn(rng, L).astype(np.complex128), storage).cuda() for (_, _, _, L) in specs]
+    x_stored = [harness.storage_to_c128(x) for x in xs]
+    refs = [ols.channel_hfso(x, n, hop, v_sets[(n, lv)], [(0, k1)] + sched.get(ci, []))
+            for ci, (x, (hop, lv, k1, L)) in enumerate(zip(x_stored, specs))]
+    for variant in (0, 1):
+        monkeypatch.setenv("VBW_VARIANT", str(variant))
+        plan = vbw.Plan(chans, pool, dtype=storage, engine="gemm", flags=vbw.F32_OUT)
+        assert plan.query(vbw.Q_VARIANT) == variant
+        for ci, entries in sched.items():
+            for frm, k1 in entries:
+                plan.set_bandwidth(ci, k1, frm)
+        ys = [torch.full((L,), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+              for (_, _, _, L) in specs]
+        run_plan(plan, xs, ys)
+        plan.close()
+        # error energy against the input's: a short channel's output can be
+        # far below the input (a one-sample channel sees only the response's
+        # tail), and the engine's error scales with its operands, not its output
+        worst = -np.inf
+        for ci, (y, ref, x) in enumerate(zip(ys, refs, x_stored)):
+            if len(ref) == 0:
+                continue
+            got = y.cpu().numpy().astype(np.complex128)
+            assert np.all(np.isfinite(got)), (storage, variant, specs[ci])
+            e = 10 * np.log10(max(np.sum(np.abs(got - ref) ** 2), 1e-300) / np.sum(np.abs(x) ** 2))
+            worst = max(worst, e)
+            assert e <= GEMM_COMPUTE_DB, (storage, variant, specs[ci], e)
+        say(storage, "gemm variant", variant, "worst error dB (vs input energy)", worst)
+
+
 STREAM_SPECS = [  # (n, hop, lv, k1, blocks per call)
     (256, 192, 8, 24, 9), (1024, 768, 16, 100, 7), (512, 256, 8, 40, 5), (64, 2, 3, 5, 40),
     (4096, 3072, 32, 200, 2), (2048, 1536, 16, 300, 3), (16, 12, 2, 3, 50),
