@@ -244,6 +244,13 @@ def test_graph_replay_matches_eager():
     pg = vbw.Plan(chans, pool, flags=vbw.GRAPH)
     s = torch.cuda.Stream()
     for rep in range(4):
+        if rep == 2:
+            # a band change between replays: the replayed graph reads the
+            # re-uploaded per-call table
+            for p in (p0, pg):
+                p.set_bandwidth(0, 200, 70)
+                p.set_bandwidth(1, 100, 10)
+            run_plan(p0, xs, eager)
         ys = [torch.full_like(x, complex(np.nan, np.nan)) for x in xs]
         with torch.cuda.stream(s):
             pg.filter(xs, ys, s)
