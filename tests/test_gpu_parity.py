@@ -818,13 +818,14 @@ def test_tuning_cache_is_written_and_read(monkeypatch, tmp_path):
     p2.close()
 
 
-@pytest.mark.parametrize("seed", [101, 202, 303])
-def test_random_plans_against_oracle(seed):
+@pytest.mark.parametrize("seed,dtype", [(101, "c64"), (202, "r32"), (303, "c64"), (404, "f16"), (505, "bf16"),
+                                        (606, "r32"), (707, "c64")])
+def test_random_plans_against_oracle(seed, dtype):
     """Seeded random plans: mixed N and hops (even N - hop), lengths from 0 to
-    a few dozen blocks, band schedules, complex or real input, pruned or not;
-    every channel against the oracle."""
+    a few dozen blocks, band schedules, complex, 16-bit or real input, pruned
+    or not; every channel against the oracle (16-bit storage: on the stored
+    input, float32 output)."""
     rng = np.random.default_rng(seed)
-    dtype = ["c64", "r32", "c64"][seed % 3]
     flags = int(rng.choice([0, vbw.NO_PRUNE, vbw.GRAPH]))
     specs, sched = [], {}
     for ci in range(16):
@@ -845,12 +846,18 @@ def test_random_plans_against_oracle(seed):
         ys = filter_real(specs, v_sets, xs, schedules=sched, flags=flags)
     else:
         xs = [crandn(rng, s[4]) for s in specs]
+        if dtype in ("f16", "bf16"):
+            xs_dev = [harness.host_to_storage(x.astype(np.complex128), dtype).cuda() for x in xs]
+            xs = [harness.storage_to_c128(x) for x in xs_dev]       # the stored input
+            flags |= vbw.F32_OUT
+        else:
+            xs_dev = [torch.from_numpy(x).cuda() for x in xs]
         chans, pool = channels_from(specs, v_sets)
-        plan = vbw.Plan(chans, pool, flags=flags)
+        plan = vbw.Plan(chans, pool, dtype=dtype, flags=flags)
         for ch, entries in sched.items():
             for frm, k1 in entries:
                 plan.set_bandwidth(ch, k1, frm)
-        xd = [torch.from_numpy(x).cuda() for x in xs]
+        xd = xs_dev
         yd = [torch.full((len(x),), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda") for x in xs]
         stream = torch.cuda.Stream()
         stream.wait_stream(torch.cuda.current_stream())
