@@ -949,3 +949,21 @@ def test_maximum_sizes():
     e = ols.error_db(ys[0], ols.channel_hfso(xs, n, hop, v, [(0, k1)]))
     say("N = 4096, L_V = 2047, k1 = 1: dB", e)
     assert e <= FP32_DB
+
+
+def test_readme_usage_example_runs():
+    """The usage example of the repository's README, run as written (design the
+    transition values, plan, change the band, filter), then checked against the
+    oracle."""
+    import re
+    readme = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "README.md")).read()
+    code = re.search(r"## Use\s+```python\n(.*?)```", readme, re.S).group(1)
+    ns = {}
+    exec(compile(code, "README.md", "exec"), ns)
+    torch.cuda.synchronize()
+    x = ns["x"].cpu().numpy().astype(np.complex128)
+    y = ns["y"].cpu().numpy().astype(np.complex128)
+    ref = ols.channel_hfso(x, 128, 96, ns["r"].v.astype(np.float32).astype(np.float64), [(0, 41), (100, 48)])
+    e = ols.error_db(y, ref)
+    say("README example dB", e)
+    assert e <= FP32_DB
