@@ -87,6 +87,16 @@ def oracle_input(w, ci: int, dtype: str):
     return wl.channel_samples(w, ci)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(w, dtype: str, budget_s: float):
     """Time the FP64 oracle on a bounded sample: seeded random blocks of
     channel 0, as many as fit the time budget at the calibrated rate."""
@@ -109,7 +119,8 @@ def cpu_baseline(w, dtype: str, budget_s: float):
     return {"value": samples / dt, "unit": "complex samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(blocks)} seeded random blocks of channel 0 (N={c.n}, hop={c.hop}), "
                       f"{samples} output samples in {dt:.1f} s; direct O(N^2) DFT/IDFT in float64, "
-                      f"OpenMP over blocks"}, (blocks, out)
+                      f"OpenMP over blocks, {threads} threads on {cpu_model()} ({os.cpu_count()} logical CPUs "
+                      f"visible)"}, (blocks, out)
 
 
 def accuracy(w, dtype, ys, oracle_sample, n_channels: int = 4):
