@@ -587,7 +587,7 @@ __device__ __forceinline__ void run_span_real(const LaunchArgs &A, const WorkIte
     using IoR = Io<Storage::R32>;
     constexpr int N = Sh::N, T = Sh::T;
     constexpr int G = kThreads / T;
-    constexpr int E = 4;
+    constexpr int E = IoR::kBytes;
     const int tid = threadIdx.x;
     const int team = tid / T;
     const int t = tid - team * T;
