@@ -332,17 +332,20 @@ def test_filter_rejects_overlap_and_null():
 
 
 def test_allocation_failure_is_reported_and_leaves_no_plan():
-    specs = [(256, 192, 8, 20, 10000, (256, 8))]
+    specs = [(256, 192, 8, 20, 52 * 192, (256, 8))]     # whole blocks: also a valid streaming plan
     chans, pool = channels_from(specs, v_for({(256, 8)}))
-    for k in range(1, 5):
-        os.environ["VBW_FAIL_DEVICE_ALLOC"] = str(k)
-        try:
-            with pytest.raises(vbw.VbwError) as e:
-                vbw.Plan(chans, pool)
-            assert e.value.status == vbw.VBW_ENOMEM
-        finally:
-            del os.environ["VBW_FAIL_DEVICE_ALLOC"]
-    vbw.Plan(chans, pool).close()
+    # every device allocation of a plan: V, twiddles, (streaming: history,
+    # block counters,) work list, ranges, per-call tables
+    for flags, n_alloc in ((0, 5), (vbw.STREAM, 7)):
+        for k in range(1, n_alloc + 1):
+            os.environ["VBW_FAIL_DEVICE_ALLOC"] = str(k)
+            try:
+                with pytest.raises(vbw.VbwError) as e:
+                    vbw.Plan(chans, pool, flags=flags)
+                assert e.value.status == vbw.VBW_ENOMEM
+            finally:
+                del os.environ["VBW_FAIL_DEVICE_ALLOC"]
+        vbw.Plan(chans, pool, flags=flags).close()
 
 
 def check_sampled(w, ys, xs_host_fn, dtype="c64", tol=FP32_DB, channels=None, n_random=6,
