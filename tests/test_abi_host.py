@@ -3,6 +3,7 @@ exports every declared function, validation returns the documented codes,
 the integer planner and bandwidth schedule agree with an independent
 enumeration, and the float32 twiddle table is correctly rounded."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -255,3 +256,22 @@ def test_binding_checks_tensor_types_and_sizes():
     with pytest.raises(ValueError, match="input must be"):
         p.filter([torch.zeros(1000, dtype=torch.complex64)], [torch.zeros(1000, dtype=torch.float32)])
     p.close()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """With the HIP library absent the binding raises (there is no CPU
+    fallback): a fresh interpreter pointed at a missing library path."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2406_14116_amd import vbw\n"
+            "try:\n"
+            "    vbw.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "    raise SystemExit(3)\n"
+            "raise SystemExit(0)\n")
+    env = dict(os.environ, VBW_LIBRARY=str(tmp_path / "absent" / "libvbw.so"), PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 3, (r.returncode, r.stdout, r.stderr)
+    assert "missing" in r.stdout
