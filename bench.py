@@ -194,14 +194,16 @@ def bench_stream(args, w, dtype):
     ys = harness.alloc_outputs(ws, dtype)
     plan = vbw.Plan.from_workload(ws, dtype=dtype, engine=args.engine, flags=args.flags | vbw.STREAM)
     stream = torch.cuda.current_stream()
+    run = plan.bind(xs, ys)          # buffers checked once; each call is the library call only
+    s = stream.cuda_stream
     for _ in range(args.warmup * C):
-        plan.filter(xs, ys, stream)
+        run(s)
     torch.cuda.synchronize()
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     t0 = time.perf_counter()
     ev[0].record(stream)
     for _ in range(args.steps * C):
-        plan.filter(xs, ys, stream)
+        run(s)
     ev[1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

@@ -842,7 +842,11 @@ vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *
 static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream) {
     if (!p || !x || !y) return VBW_EINVAL;
     if (p->host_only) return VBW_EUNSUPPORTED;
-    if (!ranges_ok(p, x, y)) return VBW_EINVAL;
+    const size_t nch = p->ch.size();
+    // pointers of the last uploaded call were checked then
+    const bool ptrs_same = p->dyn_valid && std::equal(x, x + nch, p->last_x.begin()) &&
+                           std::equal(y, y + nch, p->last_y.begin());
+    if (!ptrs_same && !ranges_ok(p, x, y)) return VBW_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int prev = 0;
     hipError_t e = hipGetDevice(&prev);
@@ -850,9 +854,6 @@ static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y
     if (prev != p->device && (e = hipSetDevice(p->device)) != hipSuccess) return from_hip(e);
 
     vbw_status st = from_hip(order_after_last(p, s));
-    const size_t nch = p->ch.size();
-    const bool ptrs_same = p->dyn_valid && std::equal(x, x + nch, p->last_x.begin()) &&
-                           std::equal(y, y + nch, p->last_y.begin());
     if (st == VBW_OK && (!ptrs_same || p->sched_dirty)) st = upload_dyn(p, x, y, s);
 
     if (st == VBW_OK && !p->items.empty() && (p->flags & VBW_AUTOTUNE) && !p->tuned) st = autotune(p, s);

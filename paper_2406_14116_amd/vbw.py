@@ -111,6 +111,15 @@ def copy(src, dst, stream=None) -> None:
         raise VbwError(rc, "vbw_copy")
 
 
+def _stream_handle(stream) -> int:
+    """hipStream_t of a torch stream, an integer handle, or (None) torch's
+    current stream."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
 class Plan:
     """One vbw_plan: channels, shared V pool, storage dtype, engine, flags.
 
@@ -182,6 +191,29 @@ class Plan:
         """Filter torch tensors: complex64 (c64 storage), (len, 2) float16 /
         bfloat16 (16-bit storage) or 1-D float32 (r32, real input); outputs
         likewise, or (len, 2) float32 / complex64 with F32_OUT.  Runs on ``stream`` (default: torch's current)."""
+        self._check_tensors(xs, ys)
+        self.filter_ptrs([t.data_ptr() for t in xs], [t.data_ptr() for t in ys], _stream_handle(stream))
+
+    def bind(self, xs, ys):
+        """Check the tensors once and return ``run(stream=None)``, which filters
+        them again on every call with nothing but the library call: the form
+        for ring-buffered streaming (same buffers, new contents each call).
+        ``run`` keeps the tensors alive."""
+        self._check_tensors(xs, ys)
+        n = max(1, self.n_channels)
+        xp = (ctypes.c_void_p * n)(*[t.data_ptr() or None for t in xs])
+        yp = (ctypes.c_void_p * n)(*[t.data_ptr() or None for t in ys])
+        xpp, ypp = ctypes.cast(xp, ctypes.c_void_p), ctypes.cast(yp, ctypes.c_void_p)
+        call = lib().vbw_filter
+
+        def run(stream=None):
+            rc = call(self.handle, xpp, ypp, _stream_handle(stream) or None)   # raises once the plan is closed
+            if rc != VBW_OK:
+                raise VbwError(rc, "vbw_filter")
+        run.tensors = (list(xs), list(ys), xp, yp)
+        return run
+
+    def _check_tensors(self, xs, ys) -> None:
         import torch
         if len(xs) != self.n_channels or len(ys) != self.n_channels:
             raise ValueError("one input and one output tensor per channel")
@@ -203,19 +235,11 @@ class Plan:
         for t in list(xs) + list(ys):
             if not t.is_cuda or not t.is_contiguous():
                 raise ValueError("tensors must be contiguous and on the GPU")
-        if stream is None:
-            stream = torch.cuda.current_stream()
-        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        self.filter_ptrs([t.data_ptr() for t in xs], [t.data_ptr() for t in ys], s)
 
     def stream_reset(self, stream=None) -> None:
         """Restart every channel's stream (STREAM plans) on ``stream``
         (default: torch's current stream)."""
-        import torch
-        if stream is None:
-            stream = torch.cuda.current_stream()
-        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        rc = lib().vbw_stream_reset(self.handle, s or None)
+        rc = lib().vbw_stream_reset(self.handle, _stream_handle(stream) or None)
         if rc != VBW_OK:
             raise VbwError(rc, "vbw_stream_reset")
 

@@ -1013,3 +1013,34 @@ def test_many_short_channels():
         worst = max(worst, e)
         assert e <= FP32_DB, (ci, s, e)
     say("many channels: worst dB (vs input energy)", worst)
+
+
+def test_bound_call_equals_filter_and_stops_after_close():
+    """Plan.bind: the tensors are checked once and every call is the library
+    call alone; on a streaming plan fed the same ring buffers with new
+    contents, the chunks equal those of filter() on a second plan, bit for
+    bit; after close the bound call raises instead of using a freed plan."""
+    n, hop, lv, k1 = 1024, 768, 16, 100
+    chunk = 6 * hop
+    rng = np.random.default_rng(61)
+    v = v_for({(n, lv)})[(n, lv)]
+    chans = [dict(n=n, hop=hop, lv=lv, v_offset=0, k1=k1, len=chunk)] * 3
+    pa = vbw.Plan(chans, v, flags=vbw.STREAM | vbw.NO_PRUNE)
+    pb = vbw.Plan(chans, v, flags=vbw.STREAM | vbw.NO_PRUNE)
+    xa = [torch.empty(chunk, dtype=torch.complex64, device="cuda") for _ in range(3)]
+    ya = [torch.empty_like(x) for x in xa]
+    run = pa.bind(xa, ya)
+    for call in range(5):
+        data = [torch.from_numpy(crandn(rng, chunk)).cuda() for _ in range(3)]
+        for x, d in zip(xa, data):
+            x.copy_(d)
+        run()
+        yb = [torch.empty_like(d) for d in data]
+        pb.filter(data, yb)
+        torch.cuda.synchronize()
+        for a, b in zip(ya, yb):
+            assert torch.equal(a.cpu().view(torch.int64), b.cpu().view(torch.int64)), call
+    pa.close()
+    pb.close()
+    with pytest.raises(RuntimeError):
+        run()
