@@ -387,6 +387,37 @@ def test_config2_full_size_sampled():
     plan.close()
 
 
+@pytest.mark.parametrize("storage,bound", [("f16", -65.0), ("bf16", -50.0)])
+def test_config4_full_size_sampled(storage, bound):
+    """Config 4 at its full size (256 channels x 2^20 16-bit pairs) in the
+    launch configuration the benchmark times, both engines: end to end
+    against the oracle on the unquantized input, and compute only (float32
+    output, oracle on the stored input) on sampled blocks."""
+    w = wl.config4(storage=storage)
+    say("config4", storage, ": uploading", len(w.channels), "channels")
+    xs = harness.upload_inputs(w, storage)
+    chans = [0, 1, 127, 255] + list(range(2, 255, 23))
+    for engine in ("fft", "gemm"):
+        ys = harness.alloc_outputs(w, storage)
+        plan = vbw.Plan.from_workload(w, engine=engine)
+        run_plan(plan, xs, ys)
+        plan.close()
+        dbs = check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci), tol=bound, channels=chans, n_random=2)
+        say("config4", storage, engine, "end-to-end dB max/median", max(dbs), float(np.median(dbs)))
+        del ys
+        ys32 = harness.alloc_outputs(w, storage, f32_out=True)
+        p32 = vbw.Plan.from_workload(w, engine=engine, flags=vbw.F32_OUT)
+        run_plan(p32, xs, ys32)
+        p32.close()
+        dbs = check_sampled(w, ys32, lambda ci: harness.storage_to_c128(xs[ci]), channels=chans, n_random=2,
+                            tol=FP32_DB if engine == "fft" else GEMM_COMPUTE_DB)
+        say("config4", storage, engine, "compute-only dB max/median", max(dbs), float(np.median(dbs)))
+        del ys32
+        torch.cuda.empty_cache()
+    del xs
+    torch.cuda.empty_cache()
+
+
 def test_config3_full_size_sampled():
     w = wl.config3()
     say("config3: uploading", len(w.channels), "channels")
