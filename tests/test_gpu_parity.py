@@ -1075,3 +1075,17 @@ def test_bound_call_equals_filter_and_stops_after_close():
     pb.close()
     with pytest.raises(RuntimeError):
         run()
+
+
+def test_reference_copy_is_exact():
+    """vbw_copy (the bandwidth reference): byte-exact for sizes around its
+    32 KiB chunks and 16-byte words, including the partial last chunk and a
+    byte tail."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(9)
+    for nbytes in (1, 15, 16, 17, 4096, 32768 - 16, 32768, 32768 + 16, 32768 * 7 + 13, (3 << 20) + 7, 1 << 28):
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda", generator=g)
+        dst = torch.zeros_like(src)
+        vbw.copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), nbytes
