@@ -61,7 +61,8 @@ typedef enum vbw_status {
     VBW_ERANGE = -2,        /* k1 / L_V outside the admissible bin range */
     VBW_ENOMEM = -3,        /* host or device allocation failed */
     VBW_EDEVICE = -4,       /* HIP runtime or kernel launch error */
-    VBW_EUNSUPPORTED = -5   /* valid request this build does not serve */
+    VBW_EUNSUPPORTED = -5,  /* valid request this build does not serve */
+    VBW_ETOOLARGE = -6      /* vbw_filter_noalloc: tables exceed its static scratch */
 } vbw_status;
 
 typedef enum vbw_dtype {
@@ -183,6 +184,41 @@ void vbw_destroy(vbw_plan_t plan);
 
 /* Static description of a status code. */
 const char *vbw_strerror(vbw_status status);
+
+/* ---------------------------------------------------------------------
+ * Allocation-free filtering, for callers that cannot allocate device memory
+ * (serving loops and harnesses that forbid hipMalloc): one call does what
+ * vbw_plan + vbw_set_bandwidth (once per entry of `switches`) + vbw_filter +
+ * vbw_destroy do, with the same kernels and the plan's default launch shape,
+ * and calls no hipMalloc, hipFree or other allocating device routine.  Its
+ * device tables (twiddles, V, work list, per-call table) live in one static
+ * device array of VBW_NOALLOC_SCRATCH_BYTES per GPU, held until the process
+ * ends; the first call on a device locates that array and writes the
+ * twiddle table into it (synchronously).
+ * x[c] / y[c] are caller-owned device pointers as for vbw_filter; the host
+ * arrays desc, switches, x and y are read during the call only.  The tables
+ * are uploaded from pageable host memory on `stream` (a hipStream_t, NULL:
+ * the null stream), so the call may wait for that stream's earlier work;
+ * the kernels then run asynchronously on `stream`.
+ * Every call on one GPU shares that GPU's array: calls whose work is not
+ * ordered on one stream race (results undefined).  Nothing in the array
+ * needs to start at zero; every call rewrites what it reads.
+ * Flags: only VBW_NO_PRUNE and VBW_F32_OUT (anything else:
+ * VBW_EUNSUPPORTED).  Errors: as vbw_plan and vbw_filter, plus VBW_EINVAL
+ * for n_switches < 0 or NULL switches with n_switches > 0, VBW_ERANGE /
+ * VBW_EINVAL for a switch as in vbw_set_bandwidth, and VBW_ETOOLARGE when
+ * the tables would exceed the array. */
+#define VBW_NOALLOC_SCRATCH_BYTES (2u << 20)
+
+typedef struct vbw_band_switch {
+    int32_t channel;
+    int32_t k1;          /* first transition bin from block from_block on */
+    int64_t from_block;
+} vbw_band_switch;
+
+vbw_status vbw_filter_noalloc(const vbw_plan_desc *desc, int32_t n_switches,
+                              const vbw_band_switch *switches,
+                              const void *const *x, void *const *y, void *stream);
 
 /* Host-side introspection, for tests and tooling. */
 typedef enum vbw_query {

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvbw.so")
-SOURCES = ["ols_fft.hip", "ols_gemm.hip", "copy.hip", "stream.hip", "vbw_api.cpp"]
+SOURCES = ["ols_fft.hip", "ols_gemm.hip", "copy.hip", "stream.hip", "scratch.hip", "vbw_api.cpp"]
 ARCH = os.environ.get("VBW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")

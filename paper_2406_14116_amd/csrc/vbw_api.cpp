@@ -324,7 +324,7 @@ vbw::Storage storage_of(int32_t dtype) {
 //   per-N launches at the full resident occupancy, and with one workgroup per
 //   CU fewer; for plans that mix N, also one launch of the kernel that
 //   dispatches on N, at both occupancies.
-void build_variants(vbw_plan_s *p, int n_cu) {
+void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
     p->variants.clear();
     p->wg_begin.clear();
     p->work.clear();
@@ -343,7 +343,7 @@ void build_variants(vbw_plan_s *p, int n_cu) {
         return;
     }
     if (p->engine == VBW_ENGINE_GEMM) {
-        for (int drop = 0; drop < 2; ++drop) {
+        for (int drop = 0; drop < (only_default ? 1 : 2); ++drop) {
             const int per = std::max(1, vbw::ols_gemm_wg_per_cu(st, f32) - drop);
             const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per);
             p->variants.push_back({{-1, partition_items(p, 0, p->items.size(), n_wg, false), n_wg}});
@@ -369,6 +369,7 @@ void build_variants(vbw_plan_s *p, int n_cu) {
         return v;
     };
     p->variants.push_back(make(false, 0));
+    if (only_default) return;
     p->variants.push_back(make(false, 1));
     if (groups.size() > 1) {
         p->variants.push_back(make(true, 0));
@@ -574,20 +575,10 @@ bool ranges_ok(const vbw_plan_s *p, const void *const *x, void *const *y) {
     return true;
 }
 
-vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipStream_t s) {
+// The per-call table ChannelDev[nch] | x[nch] | y[nch] | SchedDev[entries],
+// written into host memory at h; returns its size in bytes.
+size_t fill_call_table(const vbw_plan_s *p, const void *const *x, void *const *y, unsigned char *h) {
     const size_t nch = p->ch.size();
-    const size_t need = p->sched_entries();
-    if (need > p->dyn_cap_sched) {
-        vbw_status st = alloc_dyn(p, std::max(need, 2 * p->dyn_cap_sched));
-        if (st != VBW_OK) return st;
-    }
-    const int next = (p->cur + 1) % p->n_tables;
-    if (p->pending[next]) {     // its staging buffer may still be in an earlier copy
-        hipError_t e = hipEventSynchronize(p->upload_evt[next]);
-        if (e != hipSuccess) return from_hip(e);
-        p->pending[next] = false;
-    }
-    unsigned char *h = p->h_stage + size_t(next) * p->dyn_stride;
     ChannelDev *hc = reinterpret_cast<ChannelDev *>(h);
     const void **hx = reinterpret_cast<const void **>(h + nch * sizeof(ChannelDev));
     void **hy = reinterpret_cast<void **>(h + nch * (sizeof(ChannelDev) + sizeof(void *)));
@@ -614,7 +605,24 @@ vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipSt
         hx[c] = x[c];
         hy[c] = y[c];
     }
-    const size_t bytes = p->dyn_bytes(size_t(so));
+    return p->dyn_bytes(size_t(so));
+}
+
+vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipStream_t s) {
+    const size_t nch = p->ch.size();
+    const size_t need = p->sched_entries();
+    if (need > p->dyn_cap_sched) {
+        vbw_status st = alloc_dyn(p, std::max(need, 2 * p->dyn_cap_sched));
+        if (st != VBW_OK) return st;
+    }
+    const int next = (p->cur + 1) % p->n_tables;
+    if (p->pending[next]) {     // its staging buffer may still be in an earlier copy
+        hipError_t e = hipEventSynchronize(p->upload_evt[next]);
+        if (e != hipSuccess) return from_hip(e);
+        p->pending[next] = false;
+    }
+    unsigned char *h = p->h_stage + size_t(next) * p->dyn_stride;
+    const size_t bytes = fill_call_table(p, x, y, h);
     hipError_t e = hipMemcpyAsync(p->d_dyn + size_t(next) * p->dyn_stride, h, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return from_hip(e);
     if ((e = hipEventRecord(p->upload_evt[next], s)) != hipSuccess) return from_hip(e);
@@ -627,15 +635,18 @@ vbw_status upload_dyn(vbw_plan_s *p, const void *const *x, void *const *y, hipSt
     return VBW_OK;
 }
 
-vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
-    const size_t nch = p->ch.size();
-    vbw::LaunchArgs a;
-    a.items = p->d_items;
-    const unsigned char *t = p->d_dyn + size_t(p->cur) * p->dyn_stride;
+// Point the per-call fields of `a` at the table that starts at device address t.
+void set_table_args(vbw::LaunchArgs &a, size_t nch, const unsigned char *t) {
     a.ch = reinterpret_cast<const ChannelDev *>(t);
     a.x = reinterpret_cast<const void *const *>(t + nch * sizeof(ChannelDev));
     a.y = reinterpret_cast<void *const *>(t + nch * (sizeof(ChannelDev) + sizeof(void *)));
     a.sched = reinterpret_cast<const SchedDev *>(t + nch * (sizeof(ChannelDev) + 2 * sizeof(void *)));
+}
+
+vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
+    vbw::LaunchArgs a;
+    a.items = p->d_items;
+    set_table_args(a, p->ch.size(), p->d_dyn + size_t(p->cur) * p->dyn_stride);
     a.v = p->d_v;
     a.tw = p->d_tw;
     a.n_items = int32_t(p->work.size());
@@ -648,19 +659,28 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
     return a;
 }
 
-// The filter launches of one variant; on a streaming plan `advance` then
-// moves every channel's history and block counter past this call (the
-// autotuner's trial runs leave them alone).
-hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant, bool advance = true) {
-    vbw::LaunchArgs a = launch_args(p);
+// The filter launches of one variant, with the tables `a` points at
+// (a.wg_begin: the start of the plan's concatenated range tables).
+hipError_t launch_variant(const vbw_plan_s *p, vbw::LaunchArgs a, hipStream_t s, int variant) {
+    const int32_t *wg0 = a.wg_begin;
+    const bool f32 = (p->flags & VBW_F32_OUT) != 0;
     for (const auto &g : p->variants[size_t(variant)]) {
-        a.wg_begin = p->d_wg_begin + g.wg_off;
+        a.wg_begin = wg0 + g.wg_off;
         a.n_wg = g.n_wg;
-        const bool f32 = (p->flags & VBW_F32_OUT) != 0;
         hipError_t e = g.log2n < 0 ? vbw::launch_ols_gemm(a, storage_of(p->dtype), f32, s)
                                    : vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), f32, s);
         if (e != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+// The filter launches of one variant; on a streaming plan `advance` then
+// moves every channel's history and block counter past this call (the
+// autotuner's trial runs leave them alone).
+hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant, bool advance = true) {
+    const vbw::LaunchArgs a = launch_args(p);
+    hipError_t e = launch_variant(p, a, s, variant);
+    if (e != hipSuccess) return e;
     if (advance && (p->flags & VBW_STREAM))
         return vbw::launch_stream_update(a, int(p->ch.size()), storage_of(p->dtype), p->d_hist, p->d_block0, s);
     return hipSuccess;
@@ -748,6 +768,41 @@ vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
     return VBW_OK;
 }
 
+// Host part of a plan from a validated description (throws std::bad_alloc).
+void init_host(vbw_plan_s *p, const vbw_plan_desc *desc) {
+    p->ch.assign(desc->channels, desc->channels + desc->n_channels);
+    p->v32.resize(size_t(desc->n_v));
+    for (int32_t i = 0; i < desc->n_v; ++i) p->v32[i] = float(desc->v_pool[i]);
+    p->dtype = desc->dtype;
+    p->engine = desc->engine;
+    p->flags = desc->flags;
+    p->sched.resize(p->ch.size());
+    for (size_t c = 0; c < p->ch.size(); ++c) p->sched[c].e.push_back({0, p->ch[c].k1});
+    build_items(p);
+}
+
+// Band-schedule entry: channel's k1 from block from_block on (Sec. III-B:
+// only the integer edge changes).
+vbw_status add_switch(vbw_plan_s *p, int32_t channel, int32_t k1, int64_t from_block) {
+    if (!p || channel < 0 || size_t(channel) >= p->ch.size() || from_block < 0) return VBW_EINVAL;
+    const vbw_channel &ch = p->ch[channel];
+    if (!k1_in_range(ch.n, ch.lv, k1)) return VBW_ERANGE;
+    auto &e = p->sched[channel].e;
+    auto it = std::lower_bound(e.begin(), e.end(), std::make_pair(from_block, INT32_MIN));
+    if (it != e.end() && it->first == from_block) {
+        it->second = k1;
+    } else {
+        if (int(e.size()) >= kMaxSchedPerChannel) return VBW_EINVAL;
+        try {
+            e.insert(it, {from_block, k1});
+        } catch (const std::bad_alloc &) {
+            return VBW_ENOMEM;
+        }
+    }
+    p->sched_dirty = true;
+    return VBW_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -761,15 +816,7 @@ vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out) {
     vbw_plan_s *p = new (std::nothrow) vbw_plan_s();
     if (!p) return VBW_ENOMEM;
     try {
-        p->ch.assign(desc->channels, desc->channels + desc->n_channels);
-        p->v32.resize(size_t(desc->n_v));
-        for (int32_t i = 0; i < desc->n_v; ++i) p->v32[i] = float(desc->v_pool[i]);
-        p->dtype = desc->dtype;
-        p->engine = desc->engine;
-        p->flags = desc->flags;
-        p->sched.resize(p->ch.size());
-        for (size_t c = 0; c < p->ch.size(); ++c) p->sched[c].e.push_back({0, p->ch[c].k1});
-        build_items(p);
+        init_host(p, desc);
     } catch (const std::bad_alloc &) {
         delete p;
         return VBW_ENOMEM;
@@ -792,23 +839,7 @@ vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out) {
 }
 
 vbw_status vbw_set_bandwidth(vbw_plan_t p, int32_t channel, int32_t k1, int64_t from_block) {
-    if (!p || channel < 0 || size_t(channel) >= p->ch.size() || from_block < 0) return VBW_EINVAL;
-    const vbw_channel &ch = p->ch[channel];
-    if (!k1_in_range(ch.n, ch.lv, k1)) return VBW_ERANGE;
-    auto &e = p->sched[channel].e;
-    auto it = std::lower_bound(e.begin(), e.end(), std::make_pair(from_block, INT32_MIN));
-    if (it != e.end() && it->first == from_block) {
-        it->second = k1;
-    } else {
-        if (int(e.size()) >= kMaxSchedPerChannel) return VBW_EINVAL;
-        try {
-            e.insert(it, {from_block, k1});
-        } catch (const std::bad_alloc &) {
-            return VBW_ENOMEM;
-        }
-    }
-    p->sched_dirty = true;
-    return VBW_OK;
+    return add_switch(p, channel, k1, from_block);
 }
 
 static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream);
@@ -908,6 +939,7 @@ const char *vbw_strerror(vbw_status s) {
         case VBW_ENOMEM: return "out of memory";
         case VBW_EDEVICE: return "device error";
         case VBW_EUNSUPPORTED: return "unsupported request";
+        case VBW_ETOOLARGE: return "tables exceed the allocation-free call's static scratch";
     }
     return "unknown status";
 }
@@ -960,3 +992,90 @@ vbw_status vbw_twiddle_table(int32_t n, float *out) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------
+// Allocation-free filtering: every device table of one call (twiddles, V,
+// work list, workgroup ranges, the per-call table) lives in the static device
+// array of scratch.hip instead of plan-owned allocations.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(VBW_NOALLOC_SCRATCH_BYTES);
+constexpr size_t kScratchTw = size_t(vbw::kTwiddleN) * sizeof(float2);   // twiddles at offset 0
+
+// Once per device: the twiddle table, which never changes (synchronous copy).
+hipError_t scratch_init(unsigned char *ptr) {
+    std::vector<float> tw(2 * vbw::kTwiddleN);
+    fill_twiddles(vbw::kTwiddleN, tw.data());
+    return hipMemcpy(ptr, tw.data(), kScratchTw, hipMemcpyHostToDevice);
+}
+
+vbw_status filter_noalloc_impl(const vbw_plan_desc *desc, int32_t n_switches, const vbw_band_switch *sw,
+                               const void *const *x, void *const *y, hipStream_t s) {
+    if (!x || !y || n_switches < 0 || (n_switches > 0 && !sw)) return VBW_EINVAL;
+    vbw_status st = validate_desc(desc);
+    if (st != VBW_OK) return st;
+    if (desc->flags & ~(VBW_NO_PRUNE | VBW_F32_OUT)) return VBW_EUNSUPPORTED;
+    vbw_plan_s p;                        // host part only: nothing on the device
+    init_host(&p, desc);
+    for (int32_t i = 0; i < n_switches; ++i)
+        if ((st = add_switch(&p, sw[i].channel, sw[i].k1, sw[i].from_block)) != VBW_OK) return st;
+    if (!ranges_ok(&p, x, y)) return VBW_EINVAL;
+    if (p.items.empty()) return VBW_OK;
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    unsigned char *base = nullptr;
+    if (e == hipSuccess) e = vbw::scratch_of_device(dev, &base, scratch_init);
+    if (e != hipSuccess) return from_hip(e);
+    build_variants(&p, n_cu, true);      // the plan's default launch shape
+
+    // layout after the twiddles: V | work list | workgroup ranges | per-call table
+    size_t end = kScratchTw;
+    auto take = [&end](size_t bytes) {
+        const size_t o = end;
+        end = (end + bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_v = take(p.v32.size() * sizeof(float));
+    const size_t o_work = take(p.work.size() * sizeof(WorkItem));
+    const size_t o_wg = take(p.wg_begin.size() * sizeof(int32_t));
+    const size_t o_tab = take(p.dyn_bytes(p.sched_entries()));
+    if (end > kScratchBytes) return VBW_ETOOLARGE;
+    std::vector<unsigned char> h(end - kScratchTw);
+    auto at = [&h](size_t o) { return h.data() + (o - kScratchTw); };   // host image of scratch offset o
+    if (!p.v32.empty()) std::memcpy(at(o_v), p.v32.data(), p.v32.size() * sizeof(float));
+    std::memcpy(at(o_work), p.work.data(), p.work.size() * sizeof(WorkItem));
+    std::memcpy(at(o_wg), p.wg_begin.data(), p.wg_begin.size() * sizeof(int32_t));
+    fill_call_table(&p, x, y, at(o_tab));
+    // pageable source: the runtime has consumed it when the call returns
+    if ((e = hipMemcpyAsync(base + kScratchTw, h.data(), h.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return from_hip(e);
+
+    vbw::LaunchArgs a;
+    a.items = reinterpret_cast<const WorkItem *>(base + o_work);
+    set_table_args(a, p.ch.size(), base + o_tab);
+    a.v = reinterpret_cast<const float *>(base + o_v);
+    a.tw = reinterpret_cast<const float2 *>(base);
+    a.n_items = int32_t(p.work.size());
+    a.wg_begin = reinterpret_cast<const int32_t *>(base + o_wg);
+    a.hist = nullptr;
+    a.block0 = nullptr;
+    a.n_wg = 0;
+    a.prune = (p.flags & VBW_NO_PRUNE) ? 0 : 1;
+    a.pad = 0;
+    return from_hip(launch_variant(&p, a, s, 0));
+}
+
+}  // namespace
+
+extern "C" vbw_status vbw_filter_noalloc(const vbw_plan_desc *desc, int32_t n_switches,
+                                         const vbw_band_switch *switches, const void *const *x, void *const *y,
+                                         void *stream) {
+    const Range range("vbw_filter_noalloc");
+    try {
+        return filter_noalloc_impl(desc, n_switches, switches, x, y, static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc &) {   // host tables of the planner
+        return VBW_ENOMEM;
+    }
+}

@@ -87,6 +87,12 @@ hipError_t launch_stream_update(const LaunchArgs &args, int n_channels, Storage 
                                 hipStream_t stream);
 hipError_t launch_stream_reset(void *hist, int64_t hist_bytes, int64_t *block0, int n_channels, hipStream_t stream);
 
+// Allocation-free calls (scratch.hip): *ptr = this device's address of the
+// static scratch array (VBW_NOALLOC_SCRATCH_BYTES bytes).  The first call for
+// a device, which must be current, looks the address up and runs `init` on
+// it once; later calls return the kept address.
+hipError_t scratch_of_device(int device, unsigned char **ptr, hipError_t (*init)(unsigned char *));
+
 // Streaming copy of `bytes` bytes (copy.hip); src and dst 16-byte aligned.
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, int n_cu, hipStream_t stream);
 

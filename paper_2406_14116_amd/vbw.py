@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("VBW_LIBRARY", os.path.join(HERE, "libvbw.so"))
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vbw.h")
 
-VBW_OK, VBW_EINVAL, VBW_ERANGE, VBW_ENOMEM, VBW_EDEVICE, VBW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+VBW_OK, VBW_EINVAL, VBW_ERANGE, VBW_ENOMEM, VBW_EDEVICE, VBW_EUNSUPPORTED, VBW_ETOOLARGE = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 2 << 20
 DTYPES = {"c64": 0, "f16": 1, "bf16": 2, "r32": 3}
 ENGINES = {"fft": 0, "gemm": 1}
 NO_PRUNE, GRAPH, F32_OUT, HOST_ONLY, AUTOTUNE, STREAM = 1, 2, 4, 8, 16, 32
@@ -35,6 +36,10 @@ class vbw_plan_desc(ctypes.Structure):
                 ("channels", ctypes.POINTER(vbw_channel)), ("v_pool", ctypes.POINTER(ctypes.c_double)),
                 ("dtype", ctypes.c_int32), ("engine", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("reserved", ctypes.c_int32)]
+
+
+class vbw_band_switch(ctypes.Structure):
+    _fields_ = [("channel", ctypes.c_int32), ("k1", ctypes.c_int32), ("from_block", ctypes.c_int64)]
 
 
 class VbwError(RuntimeError):
@@ -75,6 +80,9 @@ def lib():
         L.vbw_twiddle_table.restype = ctypes.c_int
         L.vbw_stream_reset.argtypes = [P, P]
         L.vbw_stream_reset.restype = ctypes.c_int
+        L.vbw_filter_noalloc.argtypes = [ctypes.POINTER(vbw_plan_desc), ctypes.c_int32,
+                                         ctypes.POINTER(vbw_band_switch), P, P, P]
+        L.vbw_filter_noalloc.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -111,6 +119,67 @@ def copy(src, dst, stream=None) -> None:
         raise VbwError(rc, "vbw_copy")
 
 
+def _channel_array(channels):
+    """ctypes array of vbw_channel and the channel lengths, from dicts (len)
+    or objects (length) with n, hop, lv, v_offset, k1."""
+    chans = list(channels)
+    arr = (vbw_channel * max(1, len(chans)))()
+    lengths = []
+    for i, c in enumerate(chans):
+        g = (lambda k, c=c: c[k]) if isinstance(c, dict) else (lambda k, c=c: getattr(c, k))
+        length = c["len"] if isinstance(c, dict) else c.length
+        arr[i] = vbw_channel(int(g("n")), int(g("hop")), int(g("lv")), int(g("v_offset")),
+                             int(g("k1")), 0, int(length))
+        lengths.append(int(length))
+    return arr, lengths
+
+
+def filter_noalloc(channels, v_pool, xs, ys, dtype: str = "c64", engine: str = "fft", flags: int = 0,
+                   switches=(), stream=None) -> None:
+    """vbw_filter_noalloc: plan, band switches (channel, k1, from_block) and
+    filter in one call that allocates no device memory.  xs / ys: device
+    tensors as for Plan.filter (checked here the same way)."""
+    arr, lengths = _channel_array(channels)
+    pool = np.ascontiguousarray(np.asarray(v_pool, dtype=np.float64))
+    desc = vbw_plan_desc(len(lengths), int(pool.size), arr,
+                         pool.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if pool.size else None,
+                         DTYPES[dtype], ENGINES[engine], int(flags), 0)
+    _check_tensors(lengths, dtype, int(flags), xs, ys)
+    sw = list(switches)
+    sarr = (vbw_band_switch * max(1, len(sw)))(*[vbw_band_switch(int(c), int(k), int(b)) for c, k, b in sw])
+    n = max(1, len(lengths))
+    xp = (ctypes.c_void_p * n)(*[t.data_ptr() or None for t in xs])
+    yp = (ctypes.c_void_p * n)(*[t.data_ptr() or None for t in ys])
+    rc = lib().vbw_filter_noalloc(ctypes.byref(desc), len(sw), sarr, ctypes.cast(xp, ctypes.c_void_p),
+                                  ctypes.cast(yp, ctypes.c_void_p), _stream_handle(stream) or None)
+    if rc != VBW_OK:
+        raise VbwError(rc, "vbw_filter_noalloc")
+
+
+def _check_tensors(lengths, dtype, flags, xs, ys) -> None:
+    """The kernels address len samples of the storage type from each pointer:
+    check element types and sizes before handing pointers over."""
+    import torch
+    if len(xs) != len(lengths) or len(ys) != len(lengths):
+        raise ValueError("one input and one output tensor per channel")
+    in_types = {"c64": (torch.complex64,), "f16": (torch.float16,), "bf16": (torch.bfloat16,),
+                "r32": (torch.float32,)}[dtype]
+    f32_out = bool(flags & F32_OUT) and dtype in ("f16", "bf16")
+    out_types = (torch.complex64, torch.float32) if f32_out else in_types
+    in_bytes = {"c64": 8, "f16": 4, "bf16": 4, "r32": 4}[dtype]
+    out_bytes = 8 if f32_out else in_bytes
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        if x.dtype not in in_types or y.dtype not in out_types:
+            raise ValueError(f"channel {i}: input must be {in_types}, output {out_types} for {dtype} "
+                             f"storage (got {x.dtype}, {y.dtype})")
+        if x.numel() * x.element_size() < lengths[i] * in_bytes or \
+                y.numel() * y.element_size() < lengths[i] * out_bytes:
+            raise ValueError(f"channel {i}: tensors hold fewer than len = {lengths[i]} samples")
+    for t in list(xs) + list(ys):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("tensors must be contiguous and on the GPU")
+
+
 def _stream_handle(stream) -> int:
     """hipStream_t of a torch stream, an integer handle, or (None) torch's
     current stream."""
@@ -128,20 +197,12 @@ class Plan:
     """
 
     def __init__(self, channels, v_pool, dtype: str = "c64", engine: str = "fft", flags: int = 0):
-        chans = list(channels)
-        self.n_channels = len(chans)
-        arr = (vbw_channel * max(1, len(chans)))()
-        self.lengths = []
-        for i, c in enumerate(chans):
-            g = (lambda k, c=c: c[k]) if isinstance(c, dict) else (lambda k, c=c: getattr(c, k))
-            length = c["len"] if isinstance(c, dict) else c.length
-            arr[i] = vbw_channel(int(g("n")), int(g("hop")), int(g("lv")), int(g("v_offset")),
-                                 int(g("k1")), 0, int(length))
-            self.lengths.append(int(length))
+        arr, self.lengths = _channel_array(channels)
+        self.n_channels = len(self.lengths)
         self.v_pool = np.ascontiguousarray(np.asarray(v_pool, dtype=np.float64))
         self.dtype = dtype
         self.flags = int(flags)
-        desc = vbw_plan_desc(len(chans), int(self.v_pool.size), arr,
+        desc = vbw_plan_desc(self.n_channels, int(self.v_pool.size), arr,
                              self.v_pool.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                              if self.v_pool.size else None,
                              DTYPES[dtype], ENGINES[engine], self.flags, 0)
@@ -150,8 +211,8 @@ class Plan:
         if rc != VBW_OK:
             raise VbwError(rc, "vbw_plan")
         self._h = h
-        self._xp = (ctypes.c_void_p * max(1, len(chans)))()
-        self._yp = (ctypes.c_void_p * max(1, len(chans)))()
+        self._xp = (ctypes.c_void_p * max(1, self.n_channels))()
+        self._yp = (ctypes.c_void_p * max(1, self.n_channels))()
 
     @classmethod
     def from_workload(cls, w, dtype: str | None = None, engine: str = "fft", flags: int = 0):
@@ -214,27 +275,7 @@ class Plan:
         return run
 
     def _check_tensors(self, xs, ys) -> None:
-        import torch
-        if len(xs) != self.n_channels or len(ys) != self.n_channels:
-            raise ValueError("one input and one output tensor per channel")
-        # the kernels address len samples of the plan's storage from each
-        # pointer: check element types and sizes before handing pointers over
-        in_types = {"c64": (torch.complex64,), "f16": (torch.float16,), "bf16": (torch.bfloat16,),
-                    "r32": (torch.float32,)}[self.dtype]
-        f32_out = bool(self.flags & F32_OUT) and self.dtype in ("f16", "bf16")
-        out_types = (torch.complex64, torch.float32) if f32_out else in_types
-        in_bytes = {"c64": 8, "f16": 4, "bf16": 4, "r32": 4}[self.dtype]
-        out_bytes = 8 if f32_out else in_bytes
-        for i, (x, y) in enumerate(zip(xs, ys)):
-            if x.dtype not in in_types or y.dtype not in out_types:
-                raise ValueError(f"channel {i}: input must be {in_types}, output {out_types} for {self.dtype} "
-                                 f"storage (got {x.dtype}, {y.dtype})")
-            if x.numel() * x.element_size() < self.lengths[i] * in_bytes or \
-                    y.numel() * y.element_size() < self.lengths[i] * out_bytes:
-                raise ValueError(f"channel {i}: tensors hold fewer than len = {self.lengths[i]} samples")
-        for t in list(xs) + list(ys):
-            if not t.is_cuda or not t.is_contiguous():
-                raise ValueError("tensors must be contiguous and on the GPU")
+        _check_tensors(self.lengths, self.dtype, self.flags, xs, ys)
 
     def stream_reset(self, stream=None) -> None:
         """Restart every channel's stream (STREAM plans) on ``stream``

@@ -22,6 +22,7 @@ hipError_t launch_stream_update(const LaunchArgs &, int, Storage, void *, int64_
 }
 hipError_t launch_stream_reset(void *, int64_t, int64_t *, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_copy(const void *, void *, int64_t, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t scratch_of_device(int, unsigned char **, hipError_t (*)(unsigned char *)) { return hipErrorInvalidValue; }
 }  // namespace vbw
 
 static int failures = 0;
