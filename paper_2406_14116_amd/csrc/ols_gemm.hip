@@ -1,51 +1,58 @@
 // ols_gemm.hip -- overlap-save variable-bandwidth filtering with the small DFTs
-// run as dense matrix products on the gfx950 matrix cores (FP16 inputs, FP32
+// run as dense matrix products on the gfx950 matrix cores (FP16 operands, FP32
 // accumulation), for 16-bit channel storage and N = 256.
 //
 // Paper: Moryakova & Johansson, arXiv 2406.14116.  Same operation as the FFT
 // engine: Sec. II steps 1-5 with the HFSO coefficients of eqs. (5)-(6).
 //
-// The 256-point DFT is split as 16 x 16 (n = 16 n1 + n2, k = k1 + 16 k2):
-//   S1  A1[n2][k1]  = sum_n1 x[n1][n2] W[n1][k1]          (W[a][b] = w16^{ab})
-//       A1[n2][k1] *= w256^{n2 k1}
-//   S2  X[k2][k1]   = sum_n2 W[k2][n2] A1[n2][k1]          (bin k1 + 16 k2)
-//       Y = H_R X / N
-//   S3  B[k1][n2]   = sum_k2 Y[k2][k1] conj W[k2][n2]
-//       B[k1][n2]  *= conj w256^{n2 k1}
-//   S4  z[n1][n2]   = sum_k1 conj W[n1][k1] B[k1][n2]
-// Each stage is a complex 16x16x16 product done with 16x16x32 MFMAs whose K
-// dimension carries (real part, imaginary part): one MFMA per real output.
-// The accumulator layout of one MFMA (lane = 16 g + c holds rows 4g..4g+3 of
-// column c) is exactly the B operand (K = those rows) or the transposed A
-// operand of the next one, so a block never leaves the registers of its wave.
-// Precision: the DFT matrix and the FP32 intermediates enter the matrix cores
-// as hi + lo FP16 pairs (hi = RN(v), lo = RN(v - hi)); each real product is
-// hi*hi + lo*hi + hi*lo with FP32 accumulation (the lo*lo term, ~2^-22
-// relative, is dropped).  The 16-bit input samples are exact in FP16 (BF16
-// samples are rounded to FP16 first; exact for normal-range values).  The
-// intermediates grow to about 16 times the input's magnitude, so inputs must
-// stay below about 2^11 in magnitude for the FP16 operands not to overflow.
+// The 256-point DFT is split as 16 x 16 (n = 16 n1 + n2, k = k1 + 16 k2) into
+// four complex 16x16x16 products per block (S1, S2 forward; S3, S4 inverse),
+// with the twiddles w256^{n2 k1} between them; gemm_layout.h gives the lane
+// layout.  Each complex product is a set of 16x16x32 MFMAs whose contraction
+// dimension carries (real parts, imaginary parts): one MFMA per real output.
+//
+// Precision.  The DFT matrix and the FP32 intermediates enter the matrix
+// cores as hi + lo FP16 pairs (hi = RN(v), lo = RN(v - hi)); each real
+// product is hi*hi + lo*hi + hi*lo with FP32 accumulation (the lo*lo term,
+// about 2^-22 relative, is dropped).
+// Range.  Linear filtering is scale-free (Sec. II), so every block is scaled
+// by a power of two 2^s, exactly, before its first product and by 2^-s at the
+// store: s puts the block's largest |re|, |im| in [2^t, 2^(t+1)) with t = 6
+// (less when some |V(r)| exceeds 1).  The intermediates grow by at most 16 per
+// product and by the 1/16 applied with H_R, so every FP16 operand stays below
+// 2^15, and the operands of a block's large values stay in the normal range.
+// Blocks of any finite 16-bit input (FP16 subnormals to 65504, BF16 over its
+// whole range) are therefore filtered with the same relative accuracy; only
+// values below 2^-20 of their block's largest contribute with absolute error
+// (about 2^-31 of that largest).
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
-#include <algorithm>
-
+#include "gemm_layout.h"
 #include "vbw_internal.h"
 
 namespace vbw {
 namespace {
 
-typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+using namespace gemm;
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 
 constexpr int kGemmN = 256;
-constexpr int kGemmHop4 = 4;        // blocks per wave per item step
+constexpr int kWaves = kThreads / 64;
 constexpr int kBufFlags = 0x00020000;
 constexpr int kNT = 2;
-constexpr int kOutOfRange = int(0x80000000u);
-constexpr int kVCapG = 2048;
+constexpr int kOutOfRange = int(0x80000000u);   // as an unsigned offset: past every resource's end
+constexpr int kVCapG = kGemmN / 2;
+constexpr int kTarget = 6;                       // block maximum scaled into [2^6, 2^7)
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int64_t bytes) {
     const int64_t cap = 0x7ffff000;
@@ -62,32 +69,39 @@ template <typename T> __device__ __forceinline__ T ld_uniform(const T *p, int i)
 #endif
 }
 
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-
-// D += A B with A 16x32, B 32x16 (FP16), D 16x16 (FP32).  Lane 16 g + c holds
-// K entries 8g .. 8g+7 of row c of A and of column c of B, and rows 4g .. 4g+3
-// of column c of D.  Only the pairing of K entries between A and B matters, so
-// a lane's eight K entries are used as (four rows of a real part, the same
-// four rows of an imaginary part): a complex product needs one MFMA per real
-// output, and the accumulator of one stage is already the next stage's operand.
 __device__ __forceinline__ f4 mfma(h8 a, h8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 
-__device__ __forceinline__ h8 cat(h4 p, h4 q) { return h8{p[0], p[1], p[2], p[3], q[0], q[1], q[2], q[3]}; }
-
-// hi + lo split of eight FP32 values
+// ------------------------------------------------------------ hi/lo split
 struct Split {
     h8 hi, lo;
 };
-__device__ __forceinline__ Split split(f4 a, f4 b) {
-    Split s;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const float v = i < 4 ? a[i] : b[i - 4];
-        const _Float16 h = (_Float16)v;
-        s.hi[i] = h;
-        s.lo[i] = (_Float16)(v - (float)h);
-    }
-    return s;
+
+__device__ __forceinline__ uint32_t pack_f16(float a, float b) {   // RN, one v_cvt_pk_f16_f32
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, h2v));
+}
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {  // RN, one v_cvt_pk_bf16_f32
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf2v));
+}
+// FP16 pair RN(v0 - hi0), RN(v1 - hi1) for h = (hi0, hi1): one mixed-precision
+// multiply-add per value reads the FP16 half and rounds straight to FP16
+__device__ __forceinline__ uint32_t residual_pair(uint32_t h, float v0, float v1) {
+    uint32_t l;
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=&v"(l) : "v"(h), "v"(v0));
+    asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(l) : "v"(h), "v"(v1));
+    return l;
+}
+// operand (re[0..3] | im[0..3]) as hi + lo
+__device__ __forceinline__ Split split(f4 re, f4 im) {
+    u4v hi, lo;
+    hi[0] = pack_f16(re[0], re[1]);
+    hi[1] = pack_f16(re[2], re[3]);
+    hi[2] = pack_f16(im[0], im[1]);
+    hi[3] = pack_f16(im[2], im[3]);
+    lo[0] = residual_pair(hi[0], re[0], re[1]);
+    lo[1] = residual_pair(hi[1], re[2], re[3]);
+    lo[2] = residual_pair(hi[2], im[0], im[1]);
+    lo[3] = residual_pair(hi[3], im[2], im[3]);
+    return {__builtin_bit_cast(h8, hi), __builtin_bit_cast(h8, lo)};
 }
 
 // Real product of split operands: P*Q ~ Phi*Qhi + Plo*Qhi + Phi*Qlo.
@@ -95,241 +109,303 @@ __device__ __forceinline__ f4 mm3(const Split &p, const Split &q) {
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     return mfma(p.hi, q.lo, mfma(p.lo, q.hi, mfma(p.hi, q.hi, z)));
 }
-// Exact-data product (P exact in FP16): P*Qhi + P*Qlo.
+// P exact in FP16: P*Qhi + P*Qlo.
 __device__ __forceinline__ f4 mm2(h8 p, const Split &q) {
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     return mfma(p, q.lo, mfma(p, q.hi, z));
 }
 
-// Constants of one lane (lane = 16 g + c): the DFT matrix entries it feeds,
-// W[4g + j][c] = w16^{(4g + j) c} (the same in A and B layouts since W is
-// symmetric), packed as the four K-concatenations the stages use, and the four
-// inter-stage twiddles w256^{(4g + r) c}.
+// ------------------------------------------------------------ constants
+// The DFT-matrix operands each lane feeds to the four products (exponents
+// from gemm_layout.h), as the two real operands of a complex product, and
+// the four twiddles of its accumulator slots.
 struct GemmConst {
-    Split r_ni;   // [Re W | -Im W]
-    Split i_r;    // [Im W | Re W]
-    Split r_i;    // [Re W | Im W]
-    Split ni_r;   // [-Im W | Re W]
+    Split s1r, s1i;   // S1 (B = W):      [Re W | -Im W], [Im W | Re W]
+    Split s2r, s2i;   // S2 (A = W):      [Re W | -Im W], [Im W | Re W]
+    Split s3r, s3i;   // S3 (B = conj W): [Re W |  Im W], [-Im W | Re W]
+    Split s4r, s4i;   // S4 (A = conj W): [Re W |  Im W], [-Im W | Re W]
     float2 tw[4];
 };
+
+template <int (*E)(int, int, int)>
+__device__ __forceinline__ void w_entries(const float2 *tw4096, int g, int c, f4 &wr, f4 &wi) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float2 w = tw4096[256 * E(g, c, j)];   // w16^e = w4096^{256 e}
+        wr[j] = w.x;
+        wi[j] = w.y;
+    }
+}
 
 __device__ __forceinline__ void load_consts(GemmConst &k, const float2 *__restrict__ tw4096, int lane) {
     const int g = lane >> 4, c = lane & 15;
     f4 wr, wi;
+    w_entries<s1_w>(tw4096, g, c, wr, wi);
+    k.s1r = split(wr, -wi);
+    k.s1i = split(wi, wr);
+    w_entries<s2_w>(tw4096, g, c, wr, wi);
+    k.s2r = split(wr, -wi);
+    k.s2i = split(wi, wr);
+    w_entries<s3_w>(tw4096, g, c, wr, wi);
+    k.s3r = split(wr, wi);
+    k.s3i = split(-wi, wr);
+    w_entries<s4_w>(tw4096, g, c, wr, wi);
+    k.s4r = split(wr, wi);
+    k.s4i = split(-wi, wr);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int e = ((4 * g + j) * c) & 15;               // w16^e = w4096^{256 e}
-        const float2 w = tw4096[256 * e];
-        wr[j] = w.x;
-        wi[j] = w.y;
+    for (int r = 0; r < 4; ++r) k.tw[r] = tw4096[16 * tw_e(g, c, r)];
+}
+
+// ------------------------------------------------------------ block scale
+// Largest of a wave's unsigned values, in every lane (rows of 16 lanes by
+// DPP shifts, then the four row results).
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x111, 0xf, 0xf, true)));   // row_shr:1
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x112, 0xf, 0xf, true)));   // row_shr:2
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x114, 0xf, 0xf, true)));   // row_shr:4
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x118, 0xf, 0xf, true)));   // row_shr:8
+    const uint32_t a = __builtin_amdgcn_readlane(x, 15), b = __builtin_amdgcn_readlane(x, 31);
+    const uint32_t c = __builtin_amdgcn_readlane(x, 47), d = __builtin_amdgcn_readlane(x, 63);
+    return max(max(a, b), max(c, d));
+}
+
+// Largest |re|, |im| of the block's 16-bit samples as a bit pattern with the
+// sign cleared (for sign-magnitude formats integer order is value order).
+__device__ __forceinline__ uint32_t block_max_bits(const uint32_t (&u)[4]) {
+    us2 m = __builtin_bit_cast(us2, u[0] & 0x7fff7fffu);
+#pragma unroll
+    for (int j = 1; j < 4; ++j) m = __builtin_elementwise_max(m, __builtin_bit_cast(us2, u[j] & 0x7fff7fffu));
+    return wave_max(max(uint32_t(m[0]), uint32_t(m[1])));
+}
+
+// e with 2^e <= value < 2^(e+1) for a nonzero 16-bit magnitude pattern m.
+template <Storage S> __device__ __forceinline__ int exponent_of(uint32_t m) {
+    constexpr int MB = S == Storage::F16 ? 10 : 7;          // mantissa bits
+    constexpr int BIAS = S == Storage::F16 ? 15 : 127;
+    const int eb = int(m >> MB);
+    return eb ? eb - BIAS : (31 - __builtin_clz(m)) - (BIAS + MB - 1);   // subnormal: m 2^(1-BIAS-MB)
+}
+
+// ------------------------------------------------------------ one block
+template <bool F32OUT, Storage S> __device__ __forceinline__ void gstore(__amdgpu_buffer_rsrc_t r, int off, float re,
+                                                                        float im) {
+    if constexpr (F32OUT) {
+        __builtin_amdgcn_raw_buffer_store_b64(u2v{__float_as_uint(re), __float_as_uint(im)}, r, off, 0, kNT);
+    } else if constexpr (S == Storage::F16) {
+        __builtin_amdgcn_raw_buffer_store_b32(pack_f16(re, im), r, off, 0, kNT);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(pack_bf16(re, im), r, off, 0, kNT);
     }
-    k.r_ni = split(wr, -wi);
-    k.i_r = split(wi, wr);
-    k.r_i = split(wr, wi);
-    k.ni_r = split(-wi, wr);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) k.tw[r] = tw4096[(16 * (((4 * g + r) * c) & 255)) & 4095];
 }
 
 struct CF4 {
     f4 re, im;
 };
 
-template <Storage S> struct GIo;
-template <> struct GIo<Storage::F16> {
-    // (re, im) FP16 pair of one sample -> exact FP16 halves
-    __device__ static void unpack(uint32_t u, _Float16 &re, _Float16 &im) {
-        re = __builtin_bit_cast(_Float16, uint16_t(u & 0xffffu));
-        im = __builtin_bit_cast(_Float16, uint16_t(u >> 16));
-    }
-};
-template <> struct GIo<Storage::BF16> {
-    __device__ static void unpack(uint32_t u, _Float16 &re, _Float16 &im) {
-        re = (_Float16)__uint_as_float(u << 16);
-        im = (_Float16)__uint_as_float(u & 0xffff0000u);
-    }
-};
-
-// Two float32 to packed 16-bit, round to nearest even (one v_cvt_pk_* each).
-typedef float gf2v __attribute__((ext_vector_type(2)));
-typedef __bf16 gbf2v __attribute__((ext_vector_type(2)));
-typedef _Float16 gh2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t pack_bf16_rne(float re, float im) {
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(gf2v{re, im}, gbf2v));
-}
-__device__ __forceinline__ uint32_t pack_f16_rne(float re, float im) {
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(gf2v{re, im}, gh2v));
-}
-
-template <Storage S, bool F32OUT> __device__ __forceinline__ void gstore(__amdgpu_buffer_rsrc_t r, int off, float re,
-                                                                        float im) {
-    if constexpr (F32OUT) {
-        __builtin_amdgcn_raw_buffer_store_b64(u2v{__float_as_uint(re), __float_as_uint(im)}, r, off, 0, kNT);
-    } else if constexpr (S == Storage::F16) {
-        __builtin_amdgcn_raw_buffer_store_b32(pack_f16_rne(re, im), r, off, 0, kNT);
-    } else {
-        __builtin_amdgcn_raw_buffer_store_b32(pack_bf16_rne(re, im), r, off, 0, kNT);
-    }
-}
-
-// The samples of one block: base = sample index of the segment start relative
-// to the input resource (may be negative: zero history); lane (g, c) reads
-// x[n1 = 4g + j][n2 = c], j < 4.  valid = false reads past the resource's end
-// (zeros, no memory access).
-__device__ __forceinline__ void gemm_load(__amdgpu_buffer_rsrc_t xr, int base, int lane, bool valid,
-                                          uint32_t (&u)[4]) {
-    const int g = lane >> 4, c = lane & 15;
-    __builtin_amdgcn_s_setprio(1);   // loads out ahead of other waves' arithmetic
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int i = base + 16 * (4 * g + j) + c;
-        u[j] = __builtin_amdgcn_raw_buffer_load_b32(xr, valid && i >= 0 ? i * 4 : kOutOfRange, 0, kNT);
-    }
-    __builtin_amdgcn_s_setprio(0);
-}
-
-// One OLS block of N = 256 by one wave, its samples already loaded into u.
+// One OLS block of N = 256 by one wave.  u[j]: the (re, im) 16-bit pair of
+// sample 16 in_row(g, j) + c; hf[r]: H_R / 16 of the bin in slot r; tgt: the
+// exponent the block maximum is scaled to; oofs[r]: byte offset of slot r's
+// output sample from the block's first output (kOutOfRange: not kept).
 template <Storage S, bool F32OUT>
-__device__ __forceinline__ void gemm_block(const GemmConst &K, const uint32_t (&u)[4],
-                                           __amdgpu_buffer_rsrc_t yr, int obase, int hop, int k1, int lv,
-                                           const float *vl, int lane) {
-    const int g = lane >> 4, c = lane & 15;
-    // S1 operand A = x^T: lane (g, n2 = c) holds x[n1 = 4g + j][n2], j < 4
-    h4 ar, ai;
+__device__ __forceinline__ void gemm_block(const GemmConst &K, const uint32_t (&u)[4], const float (&hf)[4], int tgt,
+                                           __amdgpu_buffer_rsrc_t yr, int obyte, const int (&oofs)[4]) {
+    const uint32_t mb = block_max_bits(u);
+    const int e = mb ? exponent_of<S>(mb) : tgt;
+    const int sh = tgt - e;            // block scale 2^sh
+    const int dsc = e - tgt - 4;       // at the store: 2^-sh and the other 1/16 of 1/N
+
+    // S1 operand: the samples (FP16 as stored; BF16 scaled, then rounded to FP16)
+    u4v xa;
+    if constexpr (S == Storage::F16) {
+        xa[0] = __builtin_amdgcn_perm(u[1], u[0], 0x05040100u);   // re0 re1
+        xa[1] = __builtin_amdgcn_perm(u[3], u[2], 0x05040100u);   // re2 re3
+        xa[2] = __builtin_amdgcn_perm(u[1], u[0], 0x07060302u);   // im0 im1
+        xa[3] = __builtin_amdgcn_perm(u[3], u[2], 0x07060302u);   // im2 im3
+    } else {
+        float re[4], im[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        _Float16 re, im;
-        GIo<S>::unpack(u[j], re, im);
-        ar[j] = re;
-        ai[j] = im;
+        for (int j = 0; j < 4; ++j) {
+            re[j] = __builtin_ldexpf(__uint_as_float(u[j] << 16), sh);
+            im[j] = __builtin_ldexpf(__uint_as_float(u[j] & 0xffff0000u), sh);
+        }
+        xa[0] = pack_f16(re[0], re[1]);
+        xa[1] = pack_f16(re[2], re[3]);
+        xa[2] = pack_f16(im[0], im[1]);
+        xa[3] = pack_f16(im[2], im[3]);
     }
-    // S1: D1[n2][k1] = sum_n1 x^T[n2][n1] W[n1][k1]
+    const h8 x = __builtin_bit_cast(h8, xa);
     CF4 d;
-    {
-        const h8 xa = cat(ar, ai);
-        d.re = mm2(xa, K.r_ni);      // xr Wr - xi Wi
-        d.im = mm2(xa, K.i_r);       // xr Wi + xi Wr
-    }
-    // twiddle w256^{n2 k1}: lane (g, k1 = c) holds rows n2 = 4g + r
+    d.re = mm2(x, K.s1r);
+    d.im = mm2(x, K.s1i);
+    // twiddle w256^{n2 k1}; FP16 input takes its block scale here
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const float2 w = K.tw[r];
-        const float x = d.re[r], y = d.im[r];
-        d.re[r] = x * w.x - y * w.y;
-        d.im[r] = x * w.y + y * w.x;
+        float2 w = K.tw[r];
+        if constexpr (S == Storage::F16) w = make_float2(__builtin_ldexpf(w.x, sh), __builtin_ldexpf(w.y, sh));
+        const float a = d.re[r], b = d.im[r];
+        d.re[r] = a * w.x - b * w.y;
+        d.im[r] = a * w.y + b * w.x;
     }
-    // S2: D2[k2][k1] = sum_n2 W[k2][n2] D1[n2][k1]  (A = W, B = D1)
+    // S2: bins k = c + 16 (4g + r)
+    CF4 q;
     {
         const Split b1 = split(d.re, d.im);
-        CF4 e;
-        e.re = mm3(K.r_ni, b1);      // Wr D1r - Wi D1i
-        e.im = mm3(K.i_r, b1);       // Wi D1r + Wr D1i
-        d = e;
+        q.re = mm3(K.s2r, b1);
+        q.im = mm3(K.s2i, b1);
     }
-    // multiply: lane (g, k1 = c) holds bins k = c + 16 (4g + r).  The 1/N of
-    // the inverse is applied as 1/16 here and 1/16 at the store, which keeps
-    // every intermediate near the input's scale (FP16 operands must neither
-    // overflow nor fall into the subnormal range)
-    {
-        constexpr float inv_n = 1.0f / 16.0f;
-        const int k2 = k1 + lv - 1;
+    // H_R / 16 (the other 1/16 of the inverse's 1/N is applied at the store)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int k = c + 16 * (4 * g + r);
-            const int kk = k <= kGemmN / 2 ? k : kGemmN - k;
-            float f = kk < k1 ? inv_n : 0.0f;
-            if (kk >= k1 && kk <= k2) f = vl[kk - k1] * inv_n;
-            d.re[r] *= f;
-            d.im[r] *= f;
-        }
+    for (int r = 0; r < 4; ++r) {
+        q.re[r] *= hf[r];
+        q.im[r] *= hf[r];
     }
-    // S3: D3[k1][n2] = sum_k2 Y^T[k1][k2] conj W[k2][n2]  (A = D2^T, B = conj W)
+    // S3
     {
-        const Split a2 = split(d.re, d.im);
-        CF4 e;
-        e.re = mm3(a2, K.r_i);       // Yr Wr + Yi Wi
-        e.im = mm3(a2, K.ni_r);      // -Yr Wi + Yi Wr
-        d = e;
+        const Split a2 = split(q.re, q.im);
+        d.re = mm3(a2, K.s3r);
+        d.im = mm3(a2, K.s3i);
     }
-    // conjugate twiddle: lane (g, n2 = c) holds rows k1 = 4g + r
+    // conjugate twiddle
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const float2 w = K.tw[r];
-        const float x = d.re[r], y = d.im[r];
-        d.re[r] = x * w.x + y * w.y;
-        d.im[r] = y * w.x - x * w.y;
+        const float a = d.re[r], b = d.im[r];
+        d.re[r] = a * w.x + b * w.y;
+        d.im[r] = b * w.x - a * w.y;
     }
-    // S4: z[n1][n2] = sum_k1 conj W[n1][k1] D3[k1][n2]  (A = conj W, B = D3)
+    // S4: slot r of lane (g, c) holds z[out_row(g, r)][c]
     {
         const Split b3 = split(d.re, d.im);
-        CF4 e;
-        e.re = mm3(K.r_i, b3);       // Wr Br + Wi Bi
-        e.im = mm3(K.ni_r, b3);      // -Wi Br + Wr Bi
-        d = e;
+        q.re = mm3(K.s4r, b3);
+        q.im = mm3(K.s4i, b3);
     }
-    // keep z0(D + j), j < hop: lane (g, n2 = c) holds z[n1 = 4g + r][n2]
-    constexpr int EO = F32OUT ? 8 : 4;
-    const int dly = (kGemmN - hop) >> 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        gstore<F32OUT, S>(yr, obyte + oofs[r], __builtin_ldexpf(q.re[r], dsc), __builtin_ldexpf(q.im[r], dsc));
+}
+
+// H_R / 16 of this lane's four bins k = c + 16 (4 g + r) for the edge k1
+// (eq. (6) with the mirror H_R(N - k) = H_R(k)); vl: V staged in LDS.
+__device__ __forceinline__ void h_factors(float (&hf)[4], int lane, int k1, int lv, const float *vl) {
+    const int g = lane >> 4, c = lane & 15;
+    const int k2 = k1 + lv - 1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int j = 16 * (4 * g + r) + c - dly;
-        gstore<S, F32OUT>(yr, unsigned(j) < unsigned(hop) ? (obase + j) * EO : kOutOfRange, d.re[r] * (1.0f / 16.0f),
-                          d.im[r] * (1.0f / 16.0f));
+        const int k = c + 16 * (4 * g + r);
+        const int kk = k <= kGemmN / 2 ? k : kGemmN - k;
+        float f = kk < k1 ? 1.0f / 16.0f : 0.0f;
+        if (kk >= k1 && kk <= k2) f = vl[kk - k1] * (1.0f / 16.0f);
+        hf[r] = f;
     }
 }
 
-// Persistent launch over the same work items as the FFT engine (items of up
-// to 16 blocks of N = 256); wave w of the workgroup filters blocks 4w..4w+3 of
-// each item in turn.
+// ------------------------------------------------------------ kernel
+// Persistent launch over spans (runs of consecutive blocks of one channel):
+// wave w of the workgroup filters the contiguous quarter [w n / 4,
+// (w+1) n / 4) of each span's n blocks.  With M = 192 (CARRY) a block's
+// slot 0 is the previous block's slot 3, so each later block loads 3 of its
+// 4 slots; the next block's loads are in flight during the current block.
+template <Storage S, bool F32OUT, bool CARRY>
+__device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp, const ChannelDev &cd,
+                                         const GemmConst &K, const float *vl, int tgt, int lane, int wave) {
+    constexpr int EO = F32OUT ? 8 : 4;
+    const int g = lane >> 4, c = lane & 15;
+    const int hop = cd.hop;
+    const int n = sp.n_blocks;
+    const int lo = (wave * n) / kWaves;
+    const int cnt = ((wave + 1) * n) / kWaves - lo;
+    if (cnt <= 0) return;
+    const int64_t seg0 = int64_t(sp.first_block) * hop - (kGemmN - hop);
+    const int64_t clip = seg0 > 0 ? seg0 : 0;
+    const auto xr = make_rsrc(static_cast<const char *>(ld_uniform(A.x, sp.channel)) + clip * 4, (cd.len - clip) * 4);
+    const int64_t ob = int64_t(sp.first_block) * hop;
+    const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, sp.channel)) + ob * EO, (cd.len - ob) * EO);
+    const int base0 = int(seg0 - clip) + lo * hop;      // segment start of the wave's first block (may be < 0)
+    // per-lane byte offsets: input slot j from the segment start, output slot r
+    // from the block's first kept sample (kOutOfRange where not kept)
+    const int dly = (kGemmN - hop) >> 1;
+    int iofs[4], oofs[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) iofs[j] = 4 * (16 * in_row(g, j) + c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int jj = 16 * out_row(g, r) + c - dly;
+        oofs[r] = unsigned(jj) < unsigned(hop) ? EO * jj : kOutOfRange;
+    }
+    // band schedule: entry in force at the wave's first block (binary search),
+    // then one step forward whenever a block reaches the next entry
+    const int64_t m0 = int64_t(sp.first_block) + lo;
+    int ea = 0, eb = cd.sched_count;                 // sched[ea].from_block <= m0 < sched[eb].from_block
+    while (eb - ea > 1) {
+        const int mid = (ea + eb) >> 1;
+        if (ld_uniform(A.sched, cd.sched_begin + mid).from_block <= m0) ea = mid;
+        else eb = mid;
+    }
+    int k1 = ld_uniform(A.sched, cd.sched_begin + ea).k1;
+    int64_t next_from = ea + 1 < cd.sched_count ? ld_uniform(A.sched, cd.sched_begin + ea + 1).from_block : INT64_MAX;
+    int k1c = -1;
+    float hf[4];
+
+    uint32_t u[4], un[4];
+    // a load at a negative offset is past the resource's end as an unsigned
+    // offset and reads 0 (the zero history before sample 0)
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[j] = __builtin_amdgcn_raw_buffer_load_b32(xr, 4 * base0 + iofs[j], 0, kNT);
+    __builtin_amdgcn_s_setprio(0);
+    for (int q = 0; q < cnt; ++q) {
+        // next block's loads (past the end after the last block, so that every
+        // step issues the same number)
+        const int nb4 = q + 1 < cnt ? 4 * (base0 + (q + 1) * hop) : kOutOfRange;
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int j = CARRY ? 1 : 0; j < 4; ++j) un[j] = __builtin_amdgcn_raw_buffer_load_b32(xr, nb4 + iofs[j], 0, kNT);
+        __builtin_amdgcn_s_setprio(0);
+        const int64_t m = m0 + q;
+        if (m >= next_from) {
+            ++ea;
+            k1 = ld_uniform(A.sched, cd.sched_begin + ea).k1;
+            next_from = ea + 1 < cd.sched_count ? ld_uniform(A.sched, cd.sched_begin + ea + 1).from_block : INT64_MAX;
+        }
+        if (k1 != k1c) {
+            h_factors(hf, lane, k1, cd.lv, vl);
+            k1c = k1;
+        }
+        gemm_block<S, F32OUT>(K, u, hf, tgt, yr, EO * (lo + q) * hop, oofs);
+        if constexpr (CARRY) un[0] = u[3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) u[j] = un[j];
+    }
+}
+
 template <Storage S, bool F32OUT>
 __global__ __launch_bounds__(kThreads) void ols_gemm_kernel(const LaunchArgs A) {
     __shared__ float vlds[kVCapG];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar control flow
     GemmConst K;
     load_consts(K, A.tw, lane);
-    int v_offset = -1, lv_staged = -1;
+    int v_offset = -1, lv_staged = -1, tgt = kTarget;
     const int w = blockIdx.x;
     const int end = ld_uniform(A.wg_begin, w + 1);
     for (int i = ld_uniform(A.wg_begin, w); i < end; ++i) {
-        const WorkItem it = ld_uniform(A.items, i);
-        const ChannelDev cd = ld_uniform(A.ch, it.channel);
+        const WorkItem sp = ld_uniform(A.items, i);
+        const ChannelDev cd = ld_uniform(A.ch, sp.channel);
         if (cd.v_offset != v_offset || cd.lv != lv_staged) {
+            // stage V; a set with some |V(r)| > 1 lowers the block target so
+            // that H_R X stays in range
             __syncthreads();
             for (int q = threadIdx.x; q < cd.lv; q += kThreads) vlds[q] = A.v[cd.v_offset + q];
+            uint32_t vm = 0;
+            for (int q = lane; q < cd.lv; q += 64) vm = max(vm, __float_as_uint(fabsf(A.v[cd.v_offset + q])));
+            vm = wave_max(vm);
+            tgt = kTarget - (vm > 0x3f800000u ? int(vm >> 23) - 126 : 0);
             __syncthreads();
             v_offset = cd.v_offset;
             lv_staged = cd.lv;
         }
-        const int hop = cd.hop;
-        const int64_t seg0 = int64_t(it.first_block) * hop - (kGemmN - hop);
-        const int64_t clip = seg0 > 0 ? seg0 : 0;
-        const char *xc = static_cast<const char *>(ld_uniform(A.x, it.channel));
-        const auto xr = make_rsrc(xc + clip * 4, (cd.len - clip) * 4);
-        constexpr int EO = F32OUT ? 8 : 4;
-        const int64_t ob = int64_t(it.first_block) * hop;
-        const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, it.channel)) + ob * EO, (cd.len - ob) * EO);
-        // the next block's samples are loaded while this one is filtered; the
-        // load is issued on every step (past the end after the last block) so
-        // that the wait before the products has a fixed count
-        const int first = kGemmHop4 * wave;                  // this wave's first block of the item
-        const int nb = std::min(kGemmHop4, it.n_blocks - first);
-        const int base0 = int(seg0 - clip);
-        uint32_t u[4], un[4];
-        if (nb > 0) gemm_load(xr, base0 + first * hop, lane, true, u);
-        for (int q = 0; q < nb; ++q) {
-            const int b = first + q;                         // block within the item
-            gemm_load(xr, base0 + (b + 1) * hop, lane, q + 1 < nb, un);
-            const int64_t m = int64_t(it.first_block) + b;
-            int k1 = ld_uniform(A.sched, cd.sched_begin).k1;
-            for (int e = 1; e < cd.sched_count; ++e) {
-                const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
-                if (sd.from_block <= m) k1 = sd.k1;
-            }
-            gemm_block<S, F32OUT>(K, u, yr, b * hop, hop, k1, cd.lv, vlds, lane);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = un[j];
-        }
+        if (cd.hop == 3 * kGemmN / 4) run_span<S, F32OUT, true>(A, sp, cd, K, vlds, tgt, lane, wave);
+        else run_span<S, F32OUT, false>(A, sp, cd, K, vlds, tgt, lane, wave);
     }
 }
 

@@ -346,7 +346,7 @@ void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
         for (int drop = 0; drop < (only_default ? 1 : 2); ++drop) {
             const int per = std::max(1, vbw::ols_gemm_wg_per_cu(st, f32) - drop);
             const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per);
-            p->variants.push_back({{-1, partition_items(p, 0, p->items.size(), n_wg, false), n_wg}});
+            p->variants.push_back({{-1, partition_items(p, 0, p->items.size(), n_wg, true), n_wg}});
         }
         p->variant = 0;
         return;

@@ -546,6 +546,69 @@ def test_gemm_engine_edge_shapes_every_block(storage, monkeypatch):
         say(storage, "gemm variant", variant, "worst error dB (vs input energy)", worst)
 
 
+# Input scales over the 16-bit storage ranges: FP16 from its subnormals to
+# its largest values, BF16 far outside FP16's range both ways.
+RANGE_CASES = {
+    "f16": [2.0 ** 10, 2.0 ** 13, "max", 2.0 ** -10, 2.0 ** -20, 0.0],
+    "bf16": [2.0 ** 40, 2.0 ** -40, 2.0 ** 100, 2.0 ** -100, 1.0, 0.0],
+}
+
+
+def scaled_input(rng, length, amp):
+    if amp == "max":       # |re|, |im| up to 60000 (FP16 holds 65504)
+        return (rng.uniform(-6e4, 6e4, length) + 1j * rng.uniform(-6e4, 6e4, length)).astype(np.complex128)
+    return crandn(rng, length).astype(np.complex128) * amp
+
+
+@pytest.mark.parametrize("engine", ["gemm", "fft"])
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_16bit_input_over_the_storage_range(storage, engine):
+    """Linear filtering is scale-free (Sec. II): channels at amplitudes over
+    the storage type's whole range, a zero channel and a channel whose
+    amplitude jumps by 2^12 both ways, against the oracle on the stored input
+    (float32 output, so only the arithmetic is measured).  Per channel, and
+    per block against the energy of that block's input segment."""
+    n, hop, lv = 256, 192, 8
+    v = wl.draw_v(7, 99, n, lv)
+    rng = np.random.default_rng(2024)
+    length = 40 * hop + 17
+    xs = [scaled_input(rng, length, a) for a in RANGE_CASES[storage]]
+    burst = crandn(rng, length).astype(np.complex128)
+    burst[10 * hop:14 * hop] *= 2.0 ** 12
+    burst[20 * hop:] *= 2.0 ** -12
+    xs.append(burst)
+    chans = [dict(n=n, hop=hop, lv=lv, v_offset=0, k1=20 + 9 * i, len=length) for i in range(len(xs))]
+    stored = [harness.host_to_storage(x, storage) for x in xs]
+    x_st = [harness.storage_to_c128(t) for t in stored]
+    plan = vbw.Plan(chans, v, dtype=storage, engine=engine, flags=vbw.F32_OUT)
+    plan.set_bandwidth(0, 50, 13)
+    ys = [torch.full((length,), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda") for _ in xs]
+    run_plan(plan, [t.cuda() for t in stored], ys)
+    plan.close()
+    tol = GEMM_COMPUTE_DB if engine == "gemm" else FP32_DB
+    for ci, (x, y) in enumerate(zip(x_st, ys)):
+        sched = [(0, chans[ci]["k1"])] + ([(13, 50)] if ci == 0 else [])
+        ref = ols.channel_hfso(x, n, hop, v, sched)
+        got = y.cpu().numpy().astype(np.complex128)
+        assert np.all(np.isfinite(got)), (storage, engine, ci)
+        if not np.any(x):
+            assert not np.any(got), (storage, engine, ci)
+            continue
+        e = ols.error_db(got, ref)
+        worst = -np.inf
+        for m in range(-(-length // hop)):
+            sl = slice(m * hop, min(length, (m + 1) * hop))
+            seg = x[max(0, m * hop - (n - hop)): (m + 1) * hop]
+            if not np.any(seg):
+                continue
+            eb = 10 * np.log10(max(np.sum(np.abs(got[sl] - ref[sl]) ** 2), 1e-300) / np.sum(np.abs(seg) ** 2))
+            worst = max(worst, eb)
+        say(storage, engine, "channel", ci, "scale", RANGE_CASES[storage][ci] if ci < len(RANGE_CASES[storage])
+            else "burst", f"error {e:.1f} dB, worst block {worst:.1f} dB (vs its input)")
+        assert e <= tol, (storage, engine, ci, e)
+        assert worst <= tol, (storage, engine, ci, worst)
+
+
 STREAM_SPECS = [  # (n, hop, lv, k1, blocks per call)
     (256, 192, 8, 24, 9), (1024, 768, 16, 100, 7), (512, 256, 8, 40, 5), (64, 2, 3, 5, 40),
     (4096, 3072, 32, 200, 2), (2048, 1536, 16, 300, 3), (16, 12, 2, 3, 50),
