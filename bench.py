@@ -236,7 +236,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--flags", type=int, default=None,
+                    help="plan flags (default: AUTOTUNE|GRAPH for config 3, the batched steady state; 0 otherwise)")
     ap.add_argument("--engine", choices=("fft", "gemm"), default="fft",
                     help="gemm: matrix-core DFTs (16-bit storage, N = 256: config 4)")
     ap.add_argument("--storage", choices=("f16", "bf16"), default="f16", help="config 4 storage")
@@ -258,6 +259,8 @@ def main():
     import torch
     from paper_2406_14116_amd import harness, vbw
 
+    if args.flags is None:
+        args.flags = (vbw.AUTOTUNE | vbw.GRAPH) if args.config == 3 else 0
     w, dtype = make_workload(args.config, args.storage, args.real)
     log(f"bench: {w.name}: {len(w.channels)} channels, {w.total_samples()} samples, storage {dtype}")
     if args.copy_calibration:
@@ -277,7 +280,9 @@ def main():
     ys = harness.alloc_outputs(w, dtype)
     log(f"bench: inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
     plan = vbw.Plan.from_workload(w, dtype=dtype, engine=args.engine, flags=args.flags)
-    stream = torch.cuda.current_stream()
+    # a stream of its own (graph replay needs one other than the null stream)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
 
     for _ in range(args.warmup):
         plan.filter(xs, ys, stream)
@@ -332,7 +337,8 @@ def main():
         "config": {"workload": w.name + ("+real" if dtype == "r32" else ""), "channels": len(w.channels), "total_samples": total,
                    "total_blocks": plan.query(vbw.Q_TOTAL_BLOCKS),
                    "n": c0.n if args.config != 3 else "mixed", "hop": c0.hop if args.config != 3 else "3N/4",
-                   "storage": dtype, "engine": args.engine, "variant": plan.query(vbw.Q_VARIANT),
+                   "storage": dtype, "engine": args.engine, "flags": args.flags,
+                   "variant": plan.query(vbw.Q_VARIANT), "variants_searched": plan.query(vbw.Q_N_VARIANTS),
                    "description": w.description},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -97,9 +97,10 @@ typedef struct vbw_channel {
     int64_t len;        /* input and output length in complex samples, >= 0 */
 } vbw_channel;
 
-/* Plan description.  The library deep-copies `channels` and `v_pool`; the
- * caller may free them when vbw_plan returns.  V values are rounded to
- * float32 once, here.  `reserved` must be 0. */
+/* Plan description.  The library deep-copies `channels`, `v_pool` and
+ * `tune_cache`; the caller may free them when vbw_plan returns.  V values are
+ * rounded to float32 once, here.  `reserved` must be 0.  A zero-initialised
+ * tail (tune_cache, max_workgroups) means: no tuning file, no cap. */
 typedef struct vbw_plan_desc {
     int32_t n_channels;            /* >= 1 */
     int32_t n_v;                   /* entries in v_pool, >= 0 */
@@ -108,6 +109,11 @@ typedef struct vbw_plan_desc {
     int32_t dtype;                 /* vbw_dtype */
     int32_t engine;                /* vbw_engine */
     uint32_t flags;                /* VBW_* flags */
+    int32_t max_workgroups;        /* cap on the workgroups of each persistent
+                                      launch (0: as many as are resident);
+                                      e.g. to leave CUs to concurrent work */
+    const char *tune_cache;        /* NULL, or a file in which VBW_AUTOTUNE
+                                      keeps its choices (see vbw_filter) */
     int32_t reserved;
 } vbw_plan_desc;
 
@@ -141,6 +147,17 @@ vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out);
 vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
                              int64_t from_block);
 
+/* Fix the plan's launch variant (0 <= variant < vbw_plan_query(plan,
+ * VBW_Q_N_VARIANTS)); the autotuner then keeps it.  Variant 0 is the default
+ * shape: one persistent launch per DFT size at full residency with pruning
+ * as the flags allow; the others change the resident workgroups per CU, the
+ * grid (twice the resident count: shorter ranges per workgroup), pruning, or
+ * use one launch of the kernel that dispatches on N (plans that mix N).  All
+ * variants compute the same result (Sec. II; only the schedule changes).
+ * Errors: VBW_EINVAL (NULL plan, variant out of range); VBW_EUNSUPPORTED for
+ * a VBW_HOST_ONLY plan. */
+vbw_status vbw_plan_set_variant(vbw_plan_t plan, int32_t variant);
+
 /* Filter every channel (Sec. II steps 1-5) from zero history.
  * x[c] / y[c] are device pointers to channel c's input / output
  * (layout above); the host arrays x and y hold n_channels pointers and are
@@ -158,12 +175,14 @@ vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
  * stream state lives on the device and advances in stream order, so calls may
  * be queued (or replayed from a graph) without host synchronisation.
  * With VBW_AUTOTUNE the first call also times every launch variant on these
- * buffers (blocking; the outputs are the filter's outputs all the same) and
- * keeps the fastest for the plan's lifetime.  When the environment variable
- * VBW_TUNE_CACHE names a file, the choice is appended to it as one
- * "key variant" line (key: device, storage, engine, kernel flags and the
- * block count per N, rounded to a power of two), and a plan whose key is in
- * the file takes that variant at creation without timing.  With VBW_GRAPH and a non-null
+ * buffers (blocking; the outputs are the filter's outputs all the same),
+ * each N group's launch on its own as well, and keeps the fastest variant,
+ * or the combination of each N group's fastest launch, for the plan's
+ * lifetime.  When the plan's tune_cache names a file, the choice is appended
+ * to it as one "key choice" line (key: device, storage, engine, kernel flags,
+ * workgroup cap and the block count per N, rounded to a power of two), and a
+ * plan whose key is in the file takes that choice at creation without
+ * timing.  With VBW_GRAPH and a non-null
  * stream the launches are captured once into a HIP graph and replayed.
  * Errors: VBW_EINVAL (NULL plan or arrays, NULL pointer for a channel with
  * len > 0, an output range overlapping any other input or output range);
@@ -219,6 +238,11 @@ typedef struct vbw_band_switch {
 vbw_status vbw_filter_noalloc(const vbw_plan_desc *desc, int32_t n_switches,
                               const vbw_band_switch *switches,
                               const void *const *x, void *const *y, void *stream);
+
+/* Test hook, for tests of the allocation-failure path: the k-th device
+ * allocation (k >= 1) made by each later vbw_plan call on the calling thread
+ * fails as if the device were out of memory; k = 0 turns it off. */
+void vbw_test_fail_device_alloc(int32_t k);
 
 /* Host-side introspection, for tests and tooling. */
 typedef enum vbw_query {

@@ -383,6 +383,43 @@ constexpr int kOutOfRange = int(0x80000000u);
 
 constexpr int kVCap = 2048;  // transition values staged in LDS (L_V <= N/2 <= 2048)
 
+// Band schedule of one channel (Sec. III-B: an integer edge k1 per block),
+// walked forward: a binary search finds the entry in force at a team's first
+// block, then each later block only checks whether it has reached the next
+// entry.  Entries are sorted by from_block, the first has from_block 0.  With
+// one entry (no band change) nothing is read per block.
+struct SchedCursor {
+    int e = 0;                 // entry in force
+    int k1 = 0;
+    int64_t next = INT64_MAX;  // from_block of entry e + 1
+
+    __device__ __forceinline__ void seek(const LaunchArgs &A, const ChannelDev &cd, int64_t m) {
+        k1 = ld_uniform(A.sched, cd.sched_begin).k1;
+        e = 0;
+        next = INT64_MAX;
+        const int n = cd.sched_count;
+        if (n == 1) return;
+        int lo = 0, hi = n;                        // sched[lo].from_block <= m < sched[hi].from_block
+        for (int w = n - 1; w > 0; w >>= 1) {      // ceil(log2 n) steps, the same in every lane
+            const int mid = (lo + hi) >> 1;
+            if (mid > lo && A.sched[cd.sched_begin + mid].from_block <= m) lo = mid;
+            else if (mid > lo) hi = mid;
+        }
+        e = lo;
+        k1 = A.sched[cd.sched_begin + e].k1;
+        next = e + 1 < n ? A.sched[cd.sched_begin + e + 1].from_block : INT64_MAX;
+    }
+    // k1 of block m; m never decreases between calls
+    __device__ __forceinline__ int at(const LaunchArgs &A, const ChannelDev &cd, int64_t m) {
+        while (m >= next) {
+            ++e;
+            k1 = A.sched[cd.sched_begin + e].k1;
+            next = e + 1 < cd.sched_count ? A.sched[cd.sched_begin + e + 1].from_block : INT64_MAX;
+        }
+        return k1;
+    }
+};
+
 struct WgState {
     int v_offset = -1;   // V set currently staged in LDS
     int lv = -1;
@@ -530,15 +567,12 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
         }
     };
     gather(jb);
+    SchedCursor sc;
+    sc.seek(A, cd, mb + int64_t(sp.first_block) + lo);
     for (int s = 0; s < steps; ++s) {
         const int b = lo + s;                              // block within the span
         const bool active = s < cnt;
-        const int64_t m = mb + int64_t(sp.first_block) + b;
-        int k1 = ld_uniform(A.sched, cd.sched_begin).k1;   // last entry with from_block <= m
-        for (int e = 1; e < cd.sched_count; ++e) {
-            const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
-            if (sd.from_block <= m) k1 = sd.k1;
-        }
+        const int k1 = sc.at(A, cd, mb + int64_t(sp.first_block) + b);
         const bool more = s + 1 < steps;                   // workgroup-uniform
         // For hop = 3N/4 every sample of slots 4..15 of a block after the
         // channel's block 0 lies at index >= 0, so no history test.
@@ -628,23 +662,21 @@ __device__ __forceinline__ void run_span_real(const LaunchArgs &A, const WorkIte
             }
         }
     };
-    auto k1_of = [&](int64_t m) {   // last schedule entry with from_block <= m
-        int k1 = ld_uniform(A.sched, cd.sched_begin).k1;
-        for (int e = 1; e < cd.sched_count; ++e) {
-            const SchedDev sd = ld_uniform(A.sched, cd.sched_begin + e);
-            if (sd.from_block <= m) k1 = sd.k1;
-        }
-        return k1;
-    };
+    SchedCursor sc;
+    sc.seek(A, cd, mb + int64_t(sp.first_block) + 2 * lo);
     gather_pair(jb);
     // one filter per iteration: a pair whose blocks need different k1 takes
     // two iterations (pass 1 filters the re-gathered pair for its second block)
     int s = 0, pass = 0;
+    int k1a = 0, k1b = 0;                                   // edges of the pair's two blocks
     while (s < steps) {
         const int q = lo + s;                               // pair within the span
         const bool active = s < cnt;
-        const int64_t ma = mb + int64_t(sp.first_block) + 2 * q;
-        const int k1a = k1_of(ma), k1b = k1_of(ma + 1);
+        if (pass == 0) {                                    // the cursor only moves forward
+            const int64_t ma = mb + int64_t(sp.first_block) + 2 * q;
+            k1a = sc.at(A, cd, ma);
+            k1b = sc.at(A, cd, ma + 1);
+        }
         const bool same = k1a == k1b;
         // the second pass is taken by the whole wave (team <= one wave) or the
         // whole workgroup (teams with workgroup barriers)

@@ -46,28 +46,25 @@ struct Range {
     Range &operator=(const Range &) = delete;
 };
 
-// Test hook: VBW_FAIL_DEVICE_ALLOC=k makes the k-th device allocation made by
-// one vbw_plan call fail (1-based), to exercise the ENOMEM path without leaks.
+// Test hook (vbw_test_fail_device_alloc): the k-th device allocation made by
+// each vbw_plan call on this thread fails (1-based; 0: none), to exercise the
+// ENOMEM path without leaks.
 thread_local int g_alloc_count = 0;
+thread_local int g_fail_alloc_at = 0;
 
 hipError_t dev_alloc(void **p, size_t bytes) {
     *p = nullptr;
     ++g_alloc_count;
-    if (const char *s = std::getenv("VBW_FAIL_DEVICE_ALLOC")) {
-        if (std::atoi(s) == g_alloc_count) return hipErrorOutOfMemory;
-    }
+    if (g_fail_alloc_at > 0 && g_fail_alloc_at == g_alloc_count) return hipErrorOutOfMemory;
     if (bytes == 0) bytes = 16;
     return hipMalloc(p, bytes);
 }
 
-// Test hook: VBW_MAX_WORKGROUPS=k caps every persistent launch at k
-// workgroups, so that small inputs give each workgroup long spans.
-int wg_count(size_t tiles, size_t resident) {
+// Workgroups of one persistent launch: one per tile at most, `resident` (or
+// a multiple of it) otherwise, and at most `cap` when cap > 0.
+int wg_count(size_t tiles, size_t resident, int cap) {
     size_t n = std::min(tiles, resident);
-    if (const char *s = std::getenv("VBW_MAX_WORKGROUPS")) {
-        const long k = std::atol(s);
-        if (k > 0) n = std::min(n, size_t(k));
-    }
+    if (cap > 0) n = std::min(n, size_t(cap));
     return int(std::max<size_t>(1, n));
 }
 
@@ -146,13 +143,26 @@ struct vbw_plan_s {
     std::vector<int32_t> wg_begin;   // concatenated per-launch workgroup ranges of `work`
     // Launch variants: each is a list of persistent launches (one per N group,
     // or one launch of the kernel that dispatches on N), each with its own
-    // workgroup count and item partition.
+    // workgroup count, item partition and pruning switch.  The first ones
+    // apply one shape to every group (shape_params); after autotuning a last
+    // one may combine, per N group, the fastest of the per-N shapes.
     struct LaunchGroup {
-        int log2n;       // 0: kernel that dispatches on N
+        int log2n;       // 0: kernel that dispatches on N; -1: matrix-core kernel
         int wg_off;      // offset of this launch's range table in wg_begin
         int n_wg;
+        int prune;       // stopband-pruned passes allowed
     };
+    struct Shape {
+        int occ_drop;    // resident workgroups per CU below the kernel's maximum
+        int grid_mult;   // workgroups per launch, in units of the resident count
+        int prune;
+        bool dispatch;   // one launch of the kernel that dispatches on N
+    };
+    std::vector<Shape> shapes;
     std::vector<std::vector<LaunchGroup>> variants;
+    std::vector<int> composite;       // per-group shape index of the combined variant (if any)
+    std::string tune_cache;           // file of kept autotuner choices (empty: none)
+    int max_wg = 0;                   // cap on workgroups per launch (0: none)
     bool tuned = false;
     float *d_v = nullptr;
     void *d_hist = nullptr;           // streaming: N - hop history samples per channel
@@ -200,7 +210,7 @@ namespace {
 vbw_status validate_desc(const vbw_plan_desc *d) {
     if (!d || !d->channels || d->n_channels < 1 || d->n_v < 0 || (d->n_v > 0 && !d->v_pool))
         return VBW_EINVAL;
-    if (d->reserved != 0 || (d->flags & ~kKnownFlags) != 0) return VBW_EINVAL;
+    if (d->reserved != 0 || d->max_workgroups < 0 || (d->flags & ~kKnownFlags) != 0) return VBW_EINVAL;
     if (d->dtype != VBW_C64 && d->dtype != VBW_CF16 && d->dtype != VBW_CBF16 && d->dtype != VBW_R32)
         return VBW_EINVAL;
     if (d->engine != VBW_ENGINE_FFT && d->engine != VBW_ENGINE_GEMM) return VBW_EINVAL;
@@ -320,16 +330,24 @@ vbw::Storage storage_of(int32_t dtype) {
                                 : vbw::Storage::C64;
 }
 
-// Candidate launch shapes (the autotuner times them; variant 0 is the default):
-//   per-N launches at the full resident occupancy, and with one workgroup per
-//   CU fewer; for plans that mix N, also one launch of the kernel that
-//   dispatches on N, at both occupancies.
+// Candidate launch shapes (the autotuner times them; variant 0 is the default:
+// per-N launches, full resident occupancy, one resident grid, pruning as the
+// flags allow).  Every shape choice:
+//   resident workgroups per CU: the kernel's maximum, or one fewer;
+//   grid: the resident count, or twice it (shorter ranges, finer balance);
+//   pruning: on (when the flags allow it) or off;
+// and, for plans that mix N, one launch of the kernel that dispatches on N at
+// either occupancy.
 void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
     p->variants.clear();
+    p->shapes.clear();
+    p->composite.clear();
     p->wg_begin.clear();
     p->work.clear();
     const vbw::Storage st = storage_of(p->dtype);
     const bool f32 = (p->flags & VBW_F32_OUT) != 0;
+    const bool gemm = p->engine == VBW_ENGINE_GEMM;
+    const int prune_max = (gemm || (p->flags & VBW_NO_PRUNE)) ? 0 : 1;
     // contiguous groups of equal N
     std::vector<std::pair<size_t, size_t>> groups;
     for (size_t i = 0; i < p->items.size();) {
@@ -340,42 +358,49 @@ void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
     }
     if (groups.empty()) {
         p->variants.push_back({});
+        p->shapes.push_back({0, 1, prune_max, false});
         return;
     }
-    if (p->engine == VBW_ENGINE_GEMM) {
-        for (int drop = 0; drop < (only_default ? 1 : 2); ++drop) {
-            const int per = std::max(1, vbw::ols_gemm_wg_per_cu(st, f32) - drop);
-            const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per);
-            p->variants.push_back({{-1, partition_items(p, 0, p->items.size(), n_wg, true), n_wg}});
-        }
-        p->variant = 0;
-        return;
-    }
-    auto make = [&](bool generic, int occupancy_drop) {
+    auto per_cu = [&](int lg, int drop) {
+        return std::max(1, (gemm ? vbw::ols_gemm_wg_per_cu(st, f32) : vbw::ols_fft_wg_per_cu(lg, st, f32)) - drop);
+    };
+    auto make = [&](const vbw_plan_s::Shape &sh) {
         std::vector<vbw_plan_s::LaunchGroup> v;
-        if (generic) {
-            const int per = std::max(1, vbw::ols_fft_wg_per_cu(0, st, f32) - occupancy_drop);
-            const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per);
-            v.push_back({0, partition_items(p, 0, p->items.size(), n_wg, true), n_wg});
+        if (sh.dispatch) {
+            const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per_cu(0, sh.occ_drop) * sh.grid_mult, p->max_wg);
+            v.push_back({0, partition_items(p, 0, p->items.size(), n_wg, true), n_wg, sh.prune});
             return v;
         }
-        // one launch per N, in order on the stream, each filling the chip
+        // one launch per N (the matrix-core engine has one N), in order on
+        // the stream, each filling the chip
         for (auto &g : groups) {
             const int lg = p->items[g.first].log2n;
-            const int per = std::max(1, vbw::ols_fft_wg_per_cu(lg, st, f32) - occupancy_drop);
-            const int n_wg = wg_count(g.second - g.first, size_t(n_cu) * per);
-            v.push_back({lg, partition_items(p, g.first, g.second, n_wg, true), n_wg});
+            const int n_wg = wg_count(g.second - g.first, size_t(n_cu) * per_cu(lg, sh.occ_drop) * sh.grid_mult,
+                                      p->max_wg);
+            v.push_back({gemm ? -1 : lg, partition_items(p, g.first, g.second, n_wg, true), n_wg, sh.prune});
         }
         return v;
     };
-    p->variants.push_back(make(false, 0));
-    if (only_default) return;
-    p->variants.push_back(make(false, 1));
-    if (groups.size() > 1) {
-        p->variants.push_back(make(true, 0));
-        p->variants.push_back(make(true, 1));
-    }
+    auto add = [&](const vbw_plan_s::Shape &sh) {
+        p->shapes.push_back(sh);
+        p->variants.push_back(make(sh));
+    };
+    add({0, 1, prune_max, false});
     p->variant = 0;
+    if (only_default) return;
+    for (int prune = prune_max; prune >= 0; --prune)
+        for (int grid = 1; grid <= 2; ++grid)
+            for (int drop = 0; drop < 2; ++drop)
+                if (drop != 0 || grid != 1 || prune != prune_max) add({drop, grid, prune, false});
+    if (!gemm && groups.size() > 1)
+        for (int drop = 0; drop < 2; ++drop) add({drop, 1, prune_max, true});
+}
+
+// The variant that takes, for N group g, the launch of per-N variant choice[g].
+std::vector<vbw_plan_s::LaunchGroup> combine(const vbw_plan_s *p, const std::vector<int> &choice) {
+    std::vector<vbw_plan_s::LaunchGroup> v;
+    for (size_t g = 0; g < choice.size(); ++g) v.push_back(p->variants[size_t(choice[g])][g]);
+    return v;
 }
 
 void free_device(vbw_plan_s *p) {
@@ -461,8 +486,8 @@ vbw_status alloc_dyn(vbw_plan_s *p, size_t sched_cap) {
     return VBW_OK;
 }
 
-std::string tune_key(const vbw_plan_s *p);
-int tune_cache_lookup(const std::string &key);
+std::string tune_cache_lookup(const vbw_plan_s *p);
+void tune_cache_apply(vbw_plan_s *p, const std::string &choice);
 
 vbw_status setup_device(vbw_plan_s *p) {
     hipError_t e = hipGetDevice(&p->device);
@@ -491,22 +516,7 @@ vbw_status setup_device(vbw_plan_s *p) {
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess)
         return from_hip(e);
     build_variants(p, n_cu);
-    // Test hook: VBW_VARIANT=k fixes the launch variant (the autotuner then
-    // keeps it), so tests can run every variant.
-    if (const char *v = std::getenv("VBW_VARIANT")) {
-        const int k = std::atoi(v);
-        if (*v && k >= 0 && size_t(k) < p->variants.size()) {
-            p->variant = k;
-            p->tuned = true;
-        }
-    }
-    if ((p->flags & VBW_AUTOTUNE) && !p->tuned) {
-        const int k = tune_cache_lookup(tune_key(p));
-        if (k >= 0 && size_t(k) < p->variants.size()) {
-            p->variant = k;
-            p->tuned = true;
-        }
-    }
+    if ((p->flags & VBW_AUTOTUNE) && !p->tune_cache.empty()) tune_cache_apply(p, tune_cache_lookup(p));
     if ((e = dev_alloc(&d, std::max<size_t>(1, p->work.size()) * sizeof(WorkItem))) != hipSuccess) return from_hip(e);
     p->d_items = static_cast<WorkItem *>(d);
     if ((e = dev_alloc(&d, std::max<size_t>(1, p->wg_begin.size()) * sizeof(int32_t))) != hipSuccess)
@@ -661,17 +671,23 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
 
 // The filter launches of one variant, with the tables `a` points at
 // (a.wg_begin: the start of the plan's concatenated range tables).
-hipError_t launch_variant(const vbw_plan_s *p, vbw::LaunchArgs a, hipStream_t s, int variant) {
+hipError_t launch_variant(const vbw_plan_s *p, vbw::LaunchArgs a, hipStream_t s, int variant,
+                          hipEvent_t *marks = nullptr) {
     const int32_t *wg0 = a.wg_begin;
     const bool f32 = (p->flags & VBW_F32_OUT) != 0;
-    for (const auto &g : p->variants[size_t(variant)]) {
+    const auto &launches = p->variants[size_t(variant)];
+    for (size_t i = 0; i < launches.size(); ++i) {
+        const auto &g = launches[i];
         a.wg_begin = wg0 + g.wg_off;
         a.n_wg = g.n_wg;
-        hipError_t e = g.log2n < 0 ? vbw::launch_ols_gemm(a, storage_of(p->dtype), f32, s)
-                                   : vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), f32, s);
+        a.prune = g.prune;
+        hipError_t e = marks ? hipEventRecord(marks[i], s) : hipSuccess;
+        if (e == hipSuccess)
+            e = g.log2n < 0 ? vbw::launch_ols_gemm(a, storage_of(p->dtype), f32, s)
+                            : vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), f32, s);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return marks ? hipEventRecord(marks[launches.size()], s) : hipSuccess;
 }
 
 // The filter launches of one variant; on a streaming plan `advance` then
@@ -687,22 +703,27 @@ hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant, bool advance 
 }
 
 // Time every launch variant on the caller's buffers (filtering is idempotent:
-// each run rewrites the same outputs) and keep the fastest.  Blocking, once.
-// Tuning cache: with VBW_TUNE_CACHE=<file>, the autotuner's choice is kept
-// as one "key variant" line per plan shape and reused by later plans (and
-// processes) of the same shape instead of timing again.  The key holds the
-// device architecture and CU count, storage, engine, the flags that change
-// the kernels, and per N the log2 of the block count.
+// each run rewrites the same outputs) and keep the fastest.  The per-N
+// variants launch the N groups in the same order, so each group's launch is
+// timed on its own too; when the fastest shape differs between groups, the
+// variant that takes each group's fastest launch is added and competes on
+// the sum of those times.  Blocking, once per plan.
+// Tuning cache: with the plan's tune_cache file, the choice is kept as one
+// "key choice" line per plan shape and reused by later plans (and processes)
+// of the same shape instead of timing again.  The key holds the device
+// architecture and CU count, storage, engine, the flags that change the
+// kernels, the workgroup cap and per N the log2 of the block count; the
+// choice is a variant index, or per N group the index of its per-N variant.
 std::string tune_key(const vbw_plan_s *p) {
     hipDeviceProp_t prop;
-    std::string key = "vbw1";
+    std::string key = "vbw2";
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
         key += ":";
         for (const char *c = prop.gcnArchName; *c && *c != ':'; ++c) key += *c;
         key += ":" + std::to_string(prop.multiProcessorCount);
     }
     key += ":d" + std::to_string(p->dtype) + ":e" + std::to_string(p->engine) + ":f" +
-           std::to_string(p->flags & (VBW_NO_PRUNE | VBW_F32_OUT | VBW_STREAM));
+           std::to_string(p->flags & (VBW_NO_PRUNE | VBW_F32_OUT | VBW_STREAM)) + ":w" + std::to_string(p->max_wg);
     int64_t blocks[vbw::kMaxLog2N + 1] = {};
     for (const auto &it : p->items) blocks[it.log2n] += it.n_blocks;
     for (int lg = 0; lg <= vbw::kMaxLog2N; ++lg)
@@ -710,24 +731,58 @@ std::string tune_key(const vbw_plan_s *p) {
     return key;
 }
 
-int tune_cache_lookup(const std::string &key) {
-    const char *path = std::getenv("VBW_TUNE_CACHE");
-    if (!path || !*path) return -1;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return -1;
-    char k[1024];
-    int v = -1, found = -1;
-    while (std::fscanf(f, "%1023s %d", k, &v) == 2)
+std::string tune_cache_lookup(const vbw_plan_s *p) {
+    FILE *f = std::fopen(p->tune_cache.c_str(), "r");
+    if (!f) return std::string();
+    const std::string key = tune_key(p);
+    char k[1024], v[1024];
+    std::string found;
+    while (std::fscanf(f, "%1023s %1023s", k, v) == 2)
         if (key == k) found = v;      // the last line for a key wins
     std::fclose(f);
     return found;
 }
 
-void tune_cache_store(const std::string &key, int variant) {
-    const char *path = std::getenv("VBW_TUNE_CACHE");
-    if (!path || !*path) return;
-    if (FILE *f = std::fopen(path, "a")) {
-        std::fprintf(f, "%s %d\n", key.c_str(), variant);
+// Take a kept choice: "k" (variant k) or "k0,k1,..." (per N group, the
+// launch of per-N variant k_g).  Anything that does not fit this plan is
+// ignored (the autotuner then times again).
+void tune_cache_apply(vbw_plan_s *p, const std::string &choice) {
+    if (choice.empty()) return;
+    std::vector<int> ks;
+    size_t i = 0;
+    while (i < choice.size()) {
+        size_t j = i;
+        while (j < choice.size() && choice[j] >= '0' && choice[j] <= '9') ++j;
+        if (j == i || j - i > 6) return;
+        ks.push_back(std::atoi(choice.substr(i, j - i).c_str()));
+        if (j < choice.size() && choice[j] != ',') return;
+        i = j + 1;
+    }
+    const size_t n_var = p->variants.size();
+    if (ks.size() == 1) {
+        if (ks[0] < 0 || size_t(ks[0]) >= n_var) return;
+        p->variant = ks[0];
+    } else {
+        if (ks.size() != p->variants[0].size()) return;
+        for (int k : ks)
+            if (k < 0 || size_t(k) >= n_var || p->shapes[size_t(k)].dispatch) return;
+        p->variants.push_back(combine(p, ks));
+        p->composite = ks;
+        p->variant = int(n_var);
+    }
+    p->tuned = true;
+}
+
+void tune_cache_store(const vbw_plan_s *p) {
+    if (p->tune_cache.empty()) return;
+    std::string choice;
+    if (!p->composite.empty() && size_t(p->variant) + 1 == p->variants.size()) {
+        for (size_t g = 0; g < p->composite.size(); ++g) choice += (g ? "," : "") + std::to_string(p->composite[g]);
+    } else {
+        choice = std::to_string(p->variant);
+    }
+    if (FILE *f = std::fopen(p->tune_cache.c_str(), "a")) {
+        std::fprintf(f, "%s %s\n", tune_key(p).c_str(), choice.c_str());
         std::fclose(f);
     }
 }
@@ -738,31 +793,58 @@ vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
         p->tuned = true;
         return VBW_OK;
     }
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
+    const size_t n_groups = p->variants[0].size();
+    std::vector<hipEvent_t> ev(n_groups + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    const vbw::LaunchArgs args = launch_args(p);
     float best = 0.f;
     int best_v = 0;
+    std::vector<float> group_best(n_groups, 0.f);
+    std::vector<int> group_choice(n_groups, 0);
+    constexpr int kReps = 3;
     for (size_t v = 0; e == hipSuccess && v < p->variants.size(); ++v) {
-        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch(p, s, int(v), false);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventRecord(a, s);
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(p, s, int(v), false);
-        if (e == hipSuccess) e = hipEventRecord(b, s);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess && (v == 0 || ms < best)) {
-            best = ms;
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_variant(p, args, s, int(v));
+        std::vector<float> per(n_groups + 1, 0.f);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+            e = launch_variant(p, args, s, int(v), ev.data());
+            if (e == hipSuccess) e = hipEventSynchronize(ev[p->variants[v].size()]);
+            for (size_t g = 0; e == hipSuccess && g < p->variants[v].size(); ++g) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, ev[g], ev[g + 1]);
+                per[g] += ms;
+                per[n_groups] += ms;
+            }
+        }
+        if (e != hipSuccess) break;
+        if (v == 0 || per[n_groups] < best) {
+            best = per[n_groups];
             best_v = int(v);
         }
+        if (v < p->shapes.size() && !p->shapes[v].dispatch)
+            for (size_t g = 0; g < n_groups; ++g)
+                if (v == 0 || per[g] < group_best[g]) {
+                    group_best[g] = per[g];
+                    group_choice[g] = int(v);
+                }
     }
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return from_hip(e);
     p->variant = best_v;
+    float combined = 0.f;
+    for (float t : group_best) combined += t;
+    const bool mixed = std::any_of(group_choice.begin(), group_choice.end(),
+                                   [&](int k) { return k != group_choice[0]; });
+    if (mixed && combined < best) {
+        p->variants.push_back(combine(p, group_choice));
+        p->composite = group_choice;
+        p->variant = int(p->variants.size()) - 1;
+    }
     p->tuned = true;
     try {
-        tune_cache_store(tune_key(p), best_v);
+        tune_cache_store(p);
     } catch (const std::bad_alloc &) {
     }
     return VBW_OK;
@@ -776,6 +858,8 @@ void init_host(vbw_plan_s *p, const vbw_plan_desc *desc) {
     p->dtype = desc->dtype;
     p->engine = desc->engine;
     p->flags = desc->flags;
+    p->tune_cache = desc->tune_cache ? desc->tune_cache : "";
+    p->max_wg = desc->max_workgroups;
     p->sched.resize(p->ch.size());
     for (size_t c = 0; c < p->ch.size(); ++c) p->sched[c].e.push_back({0, p->ch[c].k1});
     build_items(p);
@@ -841,6 +925,22 @@ vbw_status vbw_plan(const vbw_plan_desc *desc, vbw_plan_t *out) {
 vbw_status vbw_set_bandwidth(vbw_plan_t p, int32_t channel, int32_t k1, int64_t from_block) {
     return add_switch(p, channel, k1, from_block);
 }
+
+vbw_status vbw_plan_set_variant(vbw_plan_t p, int32_t variant) {
+    if (!p || variant < 0 || size_t(variant) >= p->variants.size()) return VBW_EINVAL;
+    if (p->host_only) return VBW_EUNSUPPORTED;
+    if (variant != p->variant && p->graph_exec) {     // the captured graph holds the old launches
+        (void)hipGraphExecDestroy(p->graph_exec);
+        (void)hipGraphDestroy(p->graph);
+        p->graph_exec = nullptr;
+        p->graph = nullptr;
+    }
+    p->variant = variant;
+    p->tuned = true;
+    return VBW_OK;
+}
+
+void vbw_test_fail_device_alloc(int32_t k) { g_fail_alloc_at = k > 0 ? k : 0; }
 
 static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream);
 

@@ -35,7 +35,7 @@ class vbw_plan_desc(ctypes.Structure):
     _fields_ = [("n_channels", ctypes.c_int32), ("n_v", ctypes.c_int32),
                 ("channels", ctypes.POINTER(vbw_channel)), ("v_pool", ctypes.POINTER(ctypes.c_double)),
                 ("dtype", ctypes.c_int32), ("engine", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("max_workgroups", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("reserved", ctypes.c_int32)]
 
 
 class vbw_band_switch(ctypes.Structure):
@@ -83,6 +83,10 @@ def lib():
         L.vbw_filter_noalloc.argtypes = [ctypes.POINTER(vbw_plan_desc), ctypes.c_int32,
                                          ctypes.POINTER(vbw_band_switch), P, P, P]
         L.vbw_filter_noalloc.restype = ctypes.c_int
+        L.vbw_plan_set_variant.argtypes = [P, ctypes.c_int32]
+        L.vbw_plan_set_variant.restype = ctypes.c_int
+        L.vbw_test_fail_device_alloc.argtypes = [ctypes.c_int32]
+        L.vbw_test_fail_device_alloc.restype = None
         _LIB = L
     return _LIB
 
@@ -92,6 +96,12 @@ def header_functions() -> list:
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(vbw_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_fail_device_alloc(k: int) -> None:
+    """Test hook: the k-th device allocation of every later vbw_plan on this
+    thread fails (0: off)."""
+    lib().vbw_test_fail_device_alloc(int(k))
 
 
 def strerror(status: int) -> str:
@@ -135,7 +145,7 @@ def _channel_array(channels):
 
 
 def filter_noalloc(channels, v_pool, xs, ys, dtype: str = "c64", engine: str = "fft", flags: int = 0,
-                   switches=(), stream=None) -> None:
+                   switches=(), stream=None, max_workgroups: int = 0) -> None:
     """vbw_filter_noalloc: plan, band switches (channel, k1, from_block) and
     filter in one call that allocates no device memory.  xs / ys: device
     tensors as for Plan.filter (checked here the same way)."""
@@ -143,7 +153,7 @@ def filter_noalloc(channels, v_pool, xs, ys, dtype: str = "c64", engine: str = "
     pool = np.ascontiguousarray(np.asarray(v_pool, dtype=np.float64))
     desc = vbw_plan_desc(len(lengths), int(pool.size), arr,
                          pool.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if pool.size else None,
-                         DTYPES[dtype], ENGINES[engine], int(flags), 0)
+                         DTYPES[dtype], ENGINES[engine], int(flags), int(max_workgroups), None, 0)
     _check_tensors(lengths, dtype, int(flags), xs, ys)
     sw = list(switches)
     sarr = (vbw_band_switch * max(1, len(sw)))(*[vbw_band_switch(int(c), int(k), int(b)) for c, k, b in sw])
@@ -196,7 +206,8 @@ class Plan:
     k1 and len (or ``length``).
     """
 
-    def __init__(self, channels, v_pool, dtype: str = "c64", engine: str = "fft", flags: int = 0):
+    def __init__(self, channels, v_pool, dtype: str = "c64", engine: str = "fft", flags: int = 0,
+                 tune_cache: str | None = None, max_workgroups: int = 0):
         arr, self.lengths = _channel_array(channels)
         self.n_channels = len(self.lengths)
         self.v_pool = np.ascontiguousarray(np.asarray(v_pool, dtype=np.float64))
@@ -205,7 +216,8 @@ class Plan:
         desc = vbw_plan_desc(self.n_channels, int(self.v_pool.size), arr,
                              self.v_pool.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                              if self.v_pool.size else None,
-                             DTYPES[dtype], ENGINES[engine], self.flags, 0)
+                             DTYPES[dtype], ENGINES[engine], self.flags, int(max_workgroups),
+                             os.fsencode(tune_cache) if tune_cache else None, 0)
         h = ctypes.c_void_p()
         rc = lib().vbw_plan(ctypes.byref(desc), ctypes.byref(h))
         if rc != VBW_OK:
@@ -215,13 +227,13 @@ class Plan:
         self._yp = (ctypes.c_void_p * max(1, self.n_channels))()
 
     @classmethod
-    def from_workload(cls, w, dtype: str | None = None, engine: str = "fft", flags: int = 0):
+    def from_workload(cls, w, dtype: str | None = None, engine: str = "fft", flags: int = 0, **kw):
         pool, offs = w.v_pool()
         chans = [dict(n=c.n, hop=c.hop, lv=c.lv, v_offset=offs[c.v_key], k1=c.k1, len=c.length)
                  for c in w.channels]
         if dtype is None:
             dtype = {"c64": "c64", "c128": "c64", "f16": "f16", "bf16": "bf16", "r32": "r32"}[w.storage]
-        p = cls(chans, pool, dtype=dtype, engine=engine, flags=flags)
+        p = cls(chans, pool, dtype=dtype, engine=engine, flags=flags, **kw)
         for i, c in enumerate(w.channels):
             for frm, k1 in c.schedule:
                 p.set_bandwidth(i, k1, frm)
@@ -232,6 +244,12 @@ class Plan:
         if self._h is None:
             raise RuntimeError("plan destroyed")
         return self._h
+
+    def set_variant(self, variant: int) -> None:
+        """vbw_plan_set_variant: fix the launch variant."""
+        rc = lib().vbw_plan_set_variant(self.handle, int(variant))
+        if rc != VBW_OK:
+            raise VbwError(rc, "vbw_plan_set_variant")
 
     def set_bandwidth(self, channel: int, k1: int, from_block: int) -> None:
         rc = lib().vbw_set_bandwidth(self.handle, int(channel), int(k1), int(from_block))

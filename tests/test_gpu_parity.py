@@ -48,9 +48,9 @@ def crandn(rng, n):
     return ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)).astype(np.complex64)
 
 
-def filter_full(specs, v_sets, xs_host, schedules=None, flags=0):
+def filter_full(specs, v_sets, xs_host, schedules=None, flags=0, max_workgroups=0):
     chans, pool = channels_from(specs, v_sets)
-    plan = vbw.Plan(chans, pool, flags=flags)
+    plan = vbw.Plan(chans, pool, flags=flags, max_workgroups=max_workgroups)
     if schedules:
         for ch, entries in schedules.items():
             for frm, k1 in entries:
@@ -152,13 +152,12 @@ def test_edge_shapes_every_n(mixed):
 
 
 @pytest.mark.parametrize("cap", [1, 3, 7])
-def test_long_spans_every_block(monkeypatch, cap):
-    """Few workgroups (the VBW_MAX_WORKGROUPS hook) give each one long spans:
+def test_long_spans_every_block(cap):
+    """Few workgroups (the plan's max_workgroups cap) give each one long spans:
     every team walks through a run of consecutive blocks, carrying the
     overlap in registers when hop = 3N/4 (and reloading it otherwise).
     Ragged tails, runs of unequal length per team, and bandwidth changes that
     fall inside a team's run; every block is checked."""
-    monkeypatch.setenv("VBW_MAX_WORKGROUPS", str(cap))
     rng = np.random.default_rng(100 + cap)
     specs, sched = [], {}
     for n, nb in ((16, 700), (64, 300), (256, 150), (1024, 60), (4096, 21)):
@@ -169,7 +168,7 @@ def test_long_spans_every_block(monkeypatch, cap):
     v_sets = v_for({s[5] for s in specs})
     xs = [crandn(rng, s[4]) for s in specs]
     say("long spans, workgroups per launch <=", cap)
-    ys = filter_full(specs, v_sets, xs, schedules=sched)
+    ys = filter_full(specs, v_sets, xs, schedules=sched, max_workgroups=cap)
     for ci, (spec, x, y) in enumerate(zip(specs, xs, ys)):
         entries = [(0, spec[3])] + sched.get(ci, [])
         ref = oracle_full(spec, v_sets, x, entries)
@@ -194,6 +193,59 @@ def test_bandwidth_schedule_on_device():
         full_sched = [(0, spec[3])] + sched[i]
         ref = oracle_full(spec, v_sets, x, full_sched)
         assert ols.error_db(y, ref) <= FP32_DB
+
+
+@pytest.mark.parametrize("dtype,engine", [("c64", "fft"), ("r32", "fft"), ("f16", "gemm")])
+def test_4096_band_changes_on_one_channel(dtype, engine):
+    """4,096 schedule entries on one channel (the most vbw_set_bandwidth
+    keeps), at random distinct blocks: every team finds its first entry by
+    binary search and then walks forward.  Small N (several teams per wave,
+    each at its own entry), N = 256 and N = 1024; every block against the
+    oracle for N <= 256, sampled blocks for N = 1024."""
+    rng = np.random.default_rng(4096)
+    shapes = [(256, 192, 8, 5000)] if engine == "gemm" else [(64, 48, 4, 6000), (256, 192, 8, 5000),
+                                                               (1024, 768, 16, 4500)]
+    for n, hop, lv, nb in shapes:
+        length = nb * hop - 5
+        froms = np.sort(rng.choice(np.arange(1, nb), size=4095, replace=False))
+        k1s = rng.integers(1, n // 2 - lv + 1, size=4096)
+        sched = [(0, int(k1s[0]))] + [(int(f), int(k)) for f, k in zip(froms, k1s[1:])]
+        v = wl.draw_v(7, 99, n, lv)
+        chans = [dict(n=n, hop=hop, lv=lv, v_offset=0, k1=sched[0][1], len=length)]
+        plan = vbw.Plan(chans, v, dtype=dtype, engine=engine, flags=vbw.F32_OUT if dtype == "f16" else 0)
+        for f, k in sched[1:]:
+            plan.set_bandwidth(0, k, f)
+        x = crandn(rng, length).astype(np.complex128)
+        if dtype == "r32":
+            x = x.real.astype(np.float32).astype(np.complex128)
+            xd = torch.from_numpy(x.real.astype(np.float32)).cuda()
+            yd = torch.full((length,), float("nan"), dtype=torch.float32, device="cuda")
+        elif dtype == "f16":
+            st = harness.host_to_storage(x, "f16")
+            x = harness.storage_to_c128(st)
+            xd = st.cuda()
+            yd = torch.full((length,), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+        else:
+            x = x.astype(np.complex64).astype(np.complex128)
+            xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+            yd = torch.full((length,), complex(np.nan, np.nan), dtype=torch.complex64, device="cuda")
+        run_plan(plan, [xd], [yd])
+        plan.close()
+        y = harness.storage_to_c128(yd)
+        blocks = list(range(nb)) if n <= 256 else sorted(set(rng.integers(0, nb, 300).tolist()) | {0, nb - 1})
+        ref = ols.blocks_hfso(x, n, hop, v, sched, blocks=blocks)
+        got = np.concatenate([y[b * hop: min(length, (b + 1) * hop)] for b in blocks])
+        want = np.concatenate([r[: min(hop, length - b * hop)] for b, r in zip(blocks, ref)])
+        e = ols.error_db(got, want)
+        say(dtype, engine, "N", n, "4096 entries:", len(blocks), "blocks checked,", f"{e:.1f} dB")
+        assert e <= (GEMM_COMPUTE_DB if engine == "gemm" else FP32_DB), (n, e)
+        # per block: an entry applied to the wrong block gives an O(1) error there
+        pos = 0
+        for b in blocks:
+            m = min(hop, length - b * hop)
+            eb = ols.error_db(got[pos:pos + m], want[pos:pos + m])
+            assert eb <= FP32_DB + 10, (n, b, eb)
+            pos += m
 
 
 @pytest.mark.parametrize("n,hop,lv,k1", [(256, 192, 8, 24), (1024, 768, 16, 100), (4096, 3072, 32, 200),
@@ -264,11 +316,12 @@ def test_graph_replay_matches_eager():
     pg.close()
 
 
-def test_every_launch_variant_and_the_autotuner(monkeypatch):
-    """Every launch variant of a mixed-N plan (per-N launches, one launch
-    dispatching on N; two occupancies each) against the oracle, forced one at
-    a time through the VBW_VARIANT hook, eagerly and replayed from a graph;
-    then the autotuner keeps one of them."""
+def test_every_launch_variant_and_the_autotuner():
+    """Every launch variant the autotuner searches for a mixed-N plan (per-N
+    launches at two occupancies, two grid sizes, pruned or not; one launch
+    dispatching on N at two occupancies) against the oracle, fixed one at a
+    time with vbw_plan_set_variant, eagerly and replayed from a graph; then
+    the autotuner keeps one of them (possibly a per-N combination)."""
     rng = np.random.default_rng(6)
     specs = [(256, 192, 8, 20, 90000, (256, 8)), (1024, 768, 16, 100, 300000, (1024, 16)),
              (2048, 1536, 16, 300, 200000, (2048, 16)), (512, 384, 8, 50, 50000, (512, 8))]
@@ -279,13 +332,13 @@ def test_every_launch_variant_and_the_autotuner(monkeypatch):
            for x, s in zip(xs, specs)]
     p = vbw.Plan(chans, pool)
     n_var = p.query(vbw.Q_N_VARIANTS)
-    assert n_var == 4
+    assert n_var == 10
     p.close()
     stream = torch.cuda.Stream()
     for k in range(n_var):
-        monkeypatch.setenv("VBW_VARIANT", str(k))
         for flags in (0, vbw.GRAPH):
             p = vbw.Plan(chans, pool, flags=flags)
+            p.set_variant(k)
             assert p.query(vbw.Q_VARIANT) == k
             for rep in range(2):
                 with torch.cuda.stream(stream):
@@ -296,13 +349,12 @@ def test_every_launch_variant_and_the_autotuner(monkeypatch):
                 say("variant", k, "flags", flags, "call", rep, "worst dB", worst)
                 assert worst <= FP32_DB
             p.close()
-    monkeypatch.delenv("VBW_VARIANT")
     p = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE)
     ys = [torch.empty_like(x) for x in xs]
     run_plan(p, xs, ys)
     chosen = p.query(vbw.Q_VARIANT)
-    say("autotune chose variant", chosen, "grid", p.query(vbw.Q_GRID))
-    assert 0 <= chosen < n_var
+    say("autotune chose variant", chosen, "of", p.query(vbw.Q_N_VARIANTS), "grid", p.query(vbw.Q_GRID))
+    assert 0 <= chosen < p.query(vbw.Q_N_VARIANTS) <= n_var + 1
     for y, r in zip(ys, ref):
         assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
     run_plan(p, xs, ys)                      # tuned plan, second call
@@ -338,13 +390,13 @@ def test_allocation_failure_is_reported_and_leaves_no_plan():
     # block counters,) work list, ranges, per-call tables
     for flags, n_alloc in ((0, 5), (vbw.STREAM, 7)):
         for k in range(1, n_alloc + 1):
-            os.environ["VBW_FAIL_DEVICE_ALLOC"] = str(k)
+            vbw.test_fail_device_alloc(k)
             try:
                 with pytest.raises(vbw.VbwError) as e:
                     vbw.Plan(chans, pool, flags=flags)
                 assert e.value.status == vbw.VBW_ENOMEM
             finally:
-                del os.environ["VBW_FAIL_DEVICE_ALLOC"]
+                vbw.test_fail_device_alloc(0)
         vbw.Plan(chans, pool, flags=flags).close()
 
 
@@ -501,7 +553,7 @@ def test_16bit_store_is_nearest_even_of_float32_result(storage, engine):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_gemm_engine_edge_shapes_every_block(storage, monkeypatch):
+def test_gemm_engine_edge_shapes_every_block(storage):
     """The matrix-core engine (N = 256) on short and ragged channels, hops from
     2 to N - 2, the all-pass and the widest bands, band switches inside and
     between work items, and both of its launch variants: every output sample
@@ -520,9 +572,10 @@ def test_gemm_engine_edge_shapes_every_block(storage, monkeypatch):
     x_stored = [harness.storage_to_c128(x) for x in xs]
     refs = [ols.channel_hfso(x, n, hop, v_sets[(n, lv)], [(0, k1)] + sched.get(ci, []))
             for ci, (x, (hop, lv, k1, L)) in enumerate(zip(x_stored, specs))]
-    for variant in (0, 1):
-        monkeypatch.setenv("VBW_VARIANT", str(variant))
+    for variant in range(4):
         plan = vbw.Plan(chans, pool, dtype=storage, engine="gemm", flags=vbw.F32_OUT)
+        assert plan.query(vbw.Q_N_VARIANTS) == 4
+        plan.set_variant(variant)
         assert plan.query(vbw.Q_VARIANT) == variant
         for ci, entries in sched.items():
             for frm, k1 in entries:
@@ -780,9 +833,9 @@ def rrandn(rng, n):
     return rng.standard_normal(n).astype(np.float32).astype(np.float64)
 
 
-def filter_real(specs, v_sets, xs_host, schedules=None, flags=0):
+def filter_real(specs, v_sets, xs_host, schedules=None, flags=0, max_workgroups=0):
     chans, pool = channels_from(specs, v_sets)
-    plan = vbw.Plan(chans, pool, dtype="r32", flags=flags)
+    plan = vbw.Plan(chans, pool, dtype="r32", flags=flags, max_workgroups=max_workgroups)
     for ch, entries in (schedules or {}).items():
         for frm, k1 in entries:
             plan.set_bandwidth(ch, k1, frm)
@@ -832,11 +885,10 @@ def test_real_input_edge_shapes_every_n(mixed):
 
 
 @pytest.mark.parametrize("cap", [1, 5])
-def test_real_input_long_spans_and_band_switches(monkeypatch, cap):
+def test_real_input_long_spans_and_band_switches(cap):
     """Long runs of pairs per team (few workgroups), band changes at even and
     odd blocks (a change inside a pair filters that pair once per block), an
     odd number of blocks; every block against the oracle."""
-    monkeypatch.setenv("VBW_MAX_WORKGROUPS", str(cap))
     rng = np.random.default_rng(40 + cap)
     specs, sched = [], {}
     for n, nb in ((16, 301), (64, 151), (256, 75), (1024, 41), (2048, 23), (4096, 13)):
@@ -847,7 +899,7 @@ def test_real_input_long_spans_and_band_switches(monkeypatch, cap):
             specs.append((n, hop, 3, k1, nb * hop - 7, (n, 3)))
     v_sets = v_for({s[5] for s in specs})
     xs = [rrandn(rng, s[4]) for s in specs]
-    ys = filter_real(specs, v_sets, xs, schedules=sched)
+    ys = filter_real(specs, v_sets, xs, schedules=sched, max_workgroups=cap)
     for ci, (spec, x, y) in enumerate(zip(specs, xs, ys)):
         ref = oracle_real(spec, v_sets, x, [(0, spec[3])] + sched[ci])
         assert ols.error_db(y, ref) <= FP32_DB, spec
@@ -880,12 +932,12 @@ def test_real_input_config2_full_size_sampled():
     plan.close()
 
 
-def test_tuning_cache_is_written_and_read(monkeypatch, tmp_path):
-    """VBW_TUNE_CACHE: the autotuner appends its choice for the plan's shape;
-    a later plan of that shape takes the variant the file names (here edited
-    to a different one) without timing again, and still filters correctly."""
+def test_tuning_cache_is_written_and_read(tmp_path):
+    """The plan's tune_cache file: the autotuner appends its choice for the
+    plan's shape; a later plan of that shape takes the choice the file names
+    (here edited to a different variant, then to a per-N combination) without
+    timing again, and still filters correctly."""
     cache = tmp_path / "tune.txt"
-    monkeypatch.setenv("VBW_TUNE_CACHE", str(cache))
     rng = np.random.default_rng(12)
     specs = [(256, 192, 8, 20, 60000, (256, 8)), (1024, 768, 16, 100, 200000, (1024, 16))]
     v_sets = v_for({s[5] for s in specs})
@@ -893,7 +945,7 @@ def test_tuning_cache_is_written_and_read(monkeypatch, tmp_path):
     xs = [torch.from_numpy(crandn(rng, s[4])).cuda() for s in specs]
     ref = [ols.channel_hfso(x.cpu().numpy().astype(np.complex128), s[0], s[1], v_sets[s[5]], [(0, s[3])])
            for x, s in zip(xs, specs)]
-    p1 = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE)
+    p1 = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE, tune_cache=str(cache))
     n_var = p1.query(vbw.Q_N_VARIANTS)
     ys = [torch.empty_like(x) for x in xs]
     run_plan(p1, xs, ys)
@@ -901,18 +953,26 @@ def test_tuning_cache_is_written_and_read(monkeypatch, tmp_path):
     p1.close()
     lines = cache.read_text().split("\n")
     lines = [ln for ln in lines if ln.strip()]
-    assert len(lines) == 1 and lines[0].split()[1] == str(v1)
-    other = (v1 + 1) % n_var
-    cache.write_text(f"{lines[0].split()[0]} {other}\n")
-    p2 = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE)
-    assert p2.query(vbw.Q_VARIANT) == other
-    ys = [torch.empty_like(x) for x in xs]
-    run_plan(p2, xs, ys)
-    assert p2.query(vbw.Q_VARIANT) == other
-    assert len([ln for ln in cache.read_text().split("\n") if ln.strip()]) == 1   # no second timing
-    for y, r in zip(ys, ref):
-        assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
-    p2.close()
+    assert len(lines) == 1
+    key, choice = lines[0].split()
+    if "," not in choice:
+        assert choice == str(v1)
+    other = (v1 + 1) % 8      # a uniform per-N variant
+    for text, want_variant in ((f"{key} {other}\n", other), (f"{key} 3,0\n", None)):
+        cache.write_text(text)
+        p2 = vbw.Plan(chans, pool, flags=vbw.AUTOTUNE, tune_cache=str(cache))
+        got = p2.query(vbw.Q_VARIANT)
+        if want_variant is not None:
+            assert got == want_variant
+        else:                 # the combination is added as the last variant
+            assert got == p2.query(vbw.Q_N_VARIANTS) - 1 == 10
+        ys = [torch.empty_like(x) for x in xs]
+        run_plan(p2, xs, ys)
+        assert p2.query(vbw.Q_VARIANT) == got
+        assert len([ln for ln in cache.read_text().split("\n") if ln.strip()]) == 1   # no second timing
+        for y, r in zip(ys, ref):
+            assert ols.error_db(y.cpu().numpy(), r) <= FP32_DB
+        p2.close()
 
 
 @pytest.mark.parametrize("seed,dtype", [(101, "c64"), (202, "r32"), (303, "c64"), (404, "f16"), (505, "bf16"),
