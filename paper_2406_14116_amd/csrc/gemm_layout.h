@@ -16,7 +16,8 @@
 // The four products of one block (W[a][b] = w16^{ab}, w16 = exp(-j 2 pi/16)):
 //   S1  D1[n2][k1] = sum_n1 x[n1][n2] W[n1][k1]      A = input, B = W
 //   S2  X[k2][k1]  = sum_n2 W[k2][n2] T[n2][k1] D1   A = W, B = twiddled D1
-//   S3  D3[k1][n2] = sum_k2 Y[k2][k1] conj W[k2][n2] A = Y (transposed), B = conj W
+//   S3  D3[k1][n2] = sum_k2 Y[k2][k1] conj W[k2][n2] A = Y (transposed), B = W
+//                                                    (as conj(sum conj(Y) W))
 //   S4  z[n1][n2]  = sum_k1 conj W[n1][k1] T* D3     A = conj W, B = twiddled D3
 // with the twiddles T[n2][k1] = w256^{n2 k1}.  The accumulator layout of each
 // product is the next one's operand layout, so a block stays in registers.
@@ -48,7 +49,8 @@ VBW_GL_HD constexpr int out_row(int g, int r) { return transpose4(4 * g + r); }
 // contraction term j of each product.
 VBW_GL_HD constexpr int s1_w(int g, int c, int j) { return (in_row(g, j) * c) & 15; }        // W[n1][k1 = c]
 VBW_GL_HD constexpr int s2_w(int g, int c, int j) { return (c * (4 * g + j)) & 15; }         // W[k2 = c][n2]
-VBW_GL_HD constexpr int s3_w(int g, int c, int j) { return ((4 * g + j) * c) & 15; }         // W[k2][n2 = c]
+// S3's entries W[k2 = 4 g + j][n2 = c] equal S2's (W is symmetric): S3 runs
+// as the conjugate of a forward product with S2's operand.
 VBW_GL_HD constexpr int s4_w(int g, int c, int j) { return (transpose4(c) * (4 * g + j)) & 15; }  // W[n1][k1]
 // Exponent of the twiddle w256^{n2 k1} in accumulator slot r of lane (g, c)
 // (S1 output: n2 = 4 g + r, k1 = c; S3 output: k1 = 4 g + r, n2 = c).

@@ -119,10 +119,13 @@ __device__ __forceinline__ f4 mm2(h8 p, const Split &q) {
 // The DFT-matrix operands each lane feeds to the four products (exponents
 // from gemm_layout.h), as the two real operands of a complex product, and
 // the four twiddles of its accumulator slots.
+// S3's DFT-matrix entries are S2's (W is symmetric and S3's B layout is
+// S2's A layout), so S3 runs as the conjugate of a forward product:
+// sum Y conj W = conj(sum conj(Y) W), with the signs folded into the
+// neighbouring multiplies.
 struct GemmConst {
     Split s1r, s1i;   // S1 (B = W):      [Re W | -Im W], [Im W | Re W]
-    Split s2r, s2i;   // S2 (A = W):      [Re W | -Im W], [Im W | Re W]
-    Split s3r, s3i;   // S3 (B = conj W): [Re W |  Im W], [-Im W | Re W]
+    Split s2r, s2i;   // S2 (A = W) and S3 (B = W, conjugated data)
     Split s4r, s4i;   // S4 (A = conj W): [Re W |  Im W], [-Im W | Re W]
     float2 tw[4];
 };
@@ -146,9 +149,6 @@ __device__ __forceinline__ void load_consts(GemmConst &k, const float2 *__restri
     w_entries<s2_w>(tw4096, g, c, wr, wi);
     k.s2r = split(wr, -wi);
     k.s2i = split(wi, wr);
-    w_entries<s3_w>(tw4096, g, c, wr, wi);
-    k.s3r = split(wr, wi);
-    k.s3i = split(-wi, wr);
     w_entries<s4_w>(tw4096, g, c, wr, wi);
     k.s4r = split(wr, wi);
     k.s4i = split(-wi, wr);
@@ -253,25 +253,26 @@ __device__ __forceinline__ void gemm_block(const GemmConst &K, const uint32_t (&
         q.re = mm3(K.s2r, b1);
         q.im = mm3(K.s2i, b1);
     }
-    // H_R / 16 (the other 1/16 of the inverse's 1/N is applied at the store)
+    // conj(H_R Y) / 16 (the other 1/16 of the inverse's 1/N is applied at
+    // the store)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         q.re[r] *= hf[r];
-        q.im[r] *= hf[r];
+        q.im[r] *= -hf[r];
     }
-    // S3
+    // S3 as conj(sum conj(Y) W): d = -conj of the product below
     {
         const Split a2 = split(q.re, q.im);
-        d.re = mm3(a2, K.s3r);
-        d.im = mm3(a2, K.s3i);
+        d.re = mm3(a2, K.s2r);
+        d.im = mm3(a2, K.s2i);
     }
-    // conjugate twiddle
+    // conjugate twiddle of conj(d): (a - j b) conj(w)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const float2 w = K.tw[r];
         const float a = d.re[r], b = d.im[r];
-        d.re[r] = a * w.x + b * w.y;
-        d.im[r] = b * w.x - a * w.y;
+        d.re[r] = a * w.x - b * w.y;
+        d.im[r] = -(b * w.x) - a * w.y;
     }
     // S4: slot r of lane (g, c) holds z[out_row(g, r)][c]
     {

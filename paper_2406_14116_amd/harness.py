@@ -70,12 +70,13 @@ def block_slice(t, hop: int, block: int, length: int):
     return t[lo:hi]
 
 
-def sample_blocks(n_blocks: int, rng: np.random.Generator, switch_block: int | None = None,
-                  n_random: int = 8):
-    """Blocks {0, 1, s-1, s, s+1, last-1, last} plus seeded random ones."""
+def sample_blocks(n_blocks: int, rng: np.random.Generator, switch_block=None, n_random: int = 8):
+    """Blocks {0, 1, last-1, last}, {s-1, s, s+1} around the band switch s
+    (an int, or every one of an iterable), plus seeded random ones."""
     s = {0, 1, n_blocks - 2, n_blocks - 1}
-    if switch_block is not None:
-        s |= {switch_block - 1, switch_block, switch_block + 1}
+    switches = [] if switch_block is None else ([switch_block] if np.isscalar(switch_block) else list(switch_block))
+    for sw in switches:
+        s |= {int(sw) - 1, int(sw), int(sw) + 1}
     if n_blocks > 0:
         s |= set(int(b) for b in rng.integers(0, n_blocks, size=n_random))
     return sorted(b for b in s if 0 <= b < n_blocks)

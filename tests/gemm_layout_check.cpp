@@ -105,8 +105,6 @@ int main() {
         const Op s1i = make_op([](int g, int c, int j) { cd w = w16(s1_w(g, c, j)); return std::make_pair(w.imag(), w.real()); });
         const Op s2r = make_op([](int g, int c, int j) { cd w = w16(s2_w(g, c, j)); return std::make_pair(w.real(), -w.imag()); });
         const Op s2i = make_op([](int g, int c, int j) { cd w = w16(s2_w(g, c, j)); return std::make_pair(w.imag(), w.real()); });
-        const Op s3r = make_op([](int g, int c, int j) { cd w = w16(s3_w(g, c, j)); return std::make_pair(w.real(), w.imag()); });
-        const Op s3i = make_op([](int g, int c, int j) { cd w = w16(s3_w(g, c, j)); return std::make_pair(-w.imag(), w.real()); });
         const Op s4r = make_op([](int g, int c, int j) { cd w = w16(s4_w(g, c, j)); return std::make_pair(w.real(), w.imag()); });
         const Op s4i = make_op([](int g, int c, int j) { cd w = w16(s4_w(g, c, j)); return std::make_pair(-w.imag(), w.real()); });
         Acc dr = mfma(xa, s1r), di = mfma(xa, s1i);
@@ -124,12 +122,15 @@ int main() {
                 qr.v[l][r] *= f;
                 qi.v[l][r] *= f;
             }
+        // S3 = sum Y conj W = conj(sum conj(Y) W), with S2's entries
+        for (int l = 0; l < 64; ++l)
+            for (int r = 0; r < 4; ++r) qi.v[l][r] = -qi.v[l][r];
         const Op a2 = data_op(qr, qi);
-        dr = mfma(a2, s3r);
-        di = mfma(a2, s3i);
+        dr = mfma(a2, s2r);
+        di = mfma(a2, s2i);
         for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) {
-                const cd v = cd(dr.v[l][r], di.v[l][r]) * std::conj(w256(tw_e(l >> 4, l & 15, r)));
+                const cd v = cd(dr.v[l][r], -di.v[l][r]) * std::conj(w256(tw_e(l >> 4, l & 15, r)));
                 dr.v[l][r] = v.real();
                 di.v[l][r] = v.imag();
             }
