@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=None,
                     help="plan flags (default: AUTOTUNE|GRAPH for config 3, the batched steady state; 0 otherwise)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="fix the plan's launch variant (vbw_plan_set_variant) instead of the default or autotuned one")
     ap.add_argument("--engine", choices=("fft", "gemm"), default="fft",
                     help="gemm: matrix-core DFTs (16-bit storage, N = 256: config 4)")
     ap.add_argument("--storage", choices=("f16", "bf16"), default="f16", help="config 4 storage")
@@ -280,6 +282,8 @@ def main():
     ys = harness.alloc_outputs(w, dtype)
     log(f"bench: inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
     plan = vbw.Plan.from_workload(w, dtype=dtype, engine=args.engine, flags=args.flags)
+    if args.variant is not None:
+        plan.set_variant(args.variant)
     # a stream of its own (graph replay needs one other than the null stream)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()

@@ -718,9 +718,10 @@ __device__ __forceinline__ void run_span_real(const LaunchArgs &A, const WorkIte
 }
 
 // Consecutive spans [i, end) of size N: twiddles loaded once.  Returns the
-// first span index not done.
+// first span index not done.  Inlined into every kernel, so that the kernel
+// that dispatches on N has no calls (a call costs spills and a stack frame).
 template <int LOG2N, Storage S, bool F32OUT>
-__device__ int run_spans(const LaunchArgs &A, int i, int end, float2 *lds, float *vlds, float2 *cl, WgState &ws) {
+__device__ __forceinline__ int run_spans(const LaunchArgs &A, int i, int end, float2 *lds, float *vlds, float2 *cl, WgState &ws) {
     using Sh = Shape<LOG2N>;
     const int t = threadIdx.x % Sh::T;
     TwReg<LOG2N> tw;
@@ -750,7 +751,8 @@ __device__ int run_spans(const LaunchArgs &A, int i, int end, float2 *lds, float
 
 // Persistent launch: workgroup w filters spans [wg_begin[w], wg_begin[w+1]),
 // contiguous block ranges of equal estimated cost (consecutive blocks of a
-// channel stay on one CU).
+// channel stay on one CU).  In the launch that covers every N (LOG2N = 0)
+// each workgroup's range holds one N: the workgroup takes that N's path once.
 template <int LOG2N, Storage S, bool F32OUT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(VBW_WAVES_PER_EU, 8)))
 void ols_fft_kernel(const LaunchArgs A) {
@@ -759,28 +761,24 @@ void ols_fft_kernel(const LaunchArgs A) {
     __shared__ float2 clds[4 * kThreads];
     WgState ws;
     const int w = blockIdx.x;
-    int i = ld_uniform(A.wg_begin, w);
+    const int i = ld_uniform(A.wg_begin, w);
     const int end = ld_uniform(A.wg_begin, w + 1);
-    while (i < end) {
-        if constexpr (LOG2N != 0) {
-            i = run_spans<LOG2N, S, F32OUT>(A, i, end, lds, vlds, clds, ws);
-            if (i < end) i = end;   // every span of this launch has N = 2^LOG2N
-        } else {
-            switch (load_item(A, i).log2n) {
-                case 4: i = run_spans<4, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 5: i = run_spans<5, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 6: i = run_spans<6, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 7: i = run_spans<7, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 8: i = run_spans<8, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 9: i = run_spans<9, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 10: i = run_spans<10, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 11: i = run_spans<11, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                case 12: i = run_spans<12, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
-                default: i = end; break;
-            }
+    if (i >= end) return;
+    if constexpr (LOG2N != 0) {
+        run_spans<LOG2N, S, F32OUT>(A, i, end, lds, vlds, clds, ws);
+    } else {
+        switch (load_item(A, i).log2n) {
+            case 4: run_spans<4, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 5: run_spans<5, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 6: run_spans<6, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 7: run_spans<7, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 8: run_spans<8, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 9: run_spans<9, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 10: run_spans<10, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 11: run_spans<11, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            case 12: run_spans<12, S, F32OUT>(A, i, end, lds, vlds, clds, ws); break;
+            default: break;
         }
-        // a change of N changes the LDS layout: let every team finish first
-        __syncthreads();
     }
 }
 

@@ -285,12 +285,13 @@ constexpr int64_t kMaxSpanSamples = int64_t(1) << 26;
 
 // Split tiles [b, e) into n_wg contiguous ranges of equal estimated cost and
 // append the workgroups' work to p->work and their n_wg + 1 boundaries to
-// wg_begin; returns the offset of those boundaries.  A tile costs about
+// wg_begin (only the n_wg starts without `close`: the next call continues
+// the same table); returns the offset of those boundaries.  A tile costs about
 // log2(N) FFT passes plus a fixed part for loads, multiply and stores.  With
 // `spans`, consecutive tiles of one channel inside a workgroup's range merge
 // into one span, so a team filters a run of consecutive blocks and can carry
 // the overlap from one block to the next; otherwise the tiles are kept.
-int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg, bool spans) {
+int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg, bool spans, bool close = true) {
     const size_t n = e - b;
     std::vector<double> pre(n + 1, 0.0);
     for (size_t i = 0; i < n; ++i) pre[i + 1] = pre[i] + (p->items[b + i].log2n + 2.0);
@@ -319,7 +320,7 @@ int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg, bool spans) {
             p->work.push_back(it);
         }
     }
-    p->wg_begin.push_back(int32_t(p->work.size()));
+    if (close) p->wg_begin.push_back(int32_t(p->work.size()));
     return off;
 }
 
@@ -367,8 +368,27 @@ void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
     auto make = [&](const vbw_plan_s::Shape &sh) {
         std::vector<vbw_plan_s::LaunchGroup> v;
         if (sh.dispatch) {
+            // one launch; each N group gets workgroups in proportion to its
+            // cost, so that every workgroup's range holds one N
             const int n_wg = wg_count(p->items.size(), size_t(n_cu) * per_cu(0, sh.occ_drop) * sh.grid_mult, p->max_wg);
-            v.push_back({0, partition_items(p, 0, p->items.size(), n_wg, true), n_wg, sh.prune});
+            std::vector<double> cost(groups.size(), 0.0);
+            double total = 0.0;
+            for (size_t g = 0; g < groups.size(); ++g) {
+                cost[g] = double(groups[g].second - groups[g].first) * (p->items[groups[g].first].log2n + 2.0);
+                total += cost[g];
+            }
+            int off = -1, placed = 0;
+            double acc = 0.0;
+            for (size_t g = 0; g < groups.size(); ++g) {
+                acc += cost[g];
+                const int upto = g + 1 == groups.size() ? n_wg : int(std::lround(double(n_wg) * acc / total));
+                const int tiles = int(groups[g].second - groups[g].first);
+                const int k = std::max(1, std::min(tiles, upto - placed));
+                const int o = partition_items(p, groups[g].first, groups[g].second, k, true, g + 1 == groups.size());
+                if (off < 0) off = o;
+                placed += k;
+            }
+            v.push_back({0, off, placed, sh.prune});
             return v;
         }
         // one launch per N (the matrix-core engine has one N), in order on
