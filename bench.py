@@ -70,9 +70,10 @@ def make_workload(cfg: int, storage: str, real: bool = False):
     raise SystemExit(f"config {cfg} is not a bench workload (2, 3, 4, 5)")
 
 
-def workload_key(cfg: int, storage: str, engine: str, real: bool = False) -> str:
-    return {2: "fp32_64ch_n1024", 3: "batched_512ch_mixed", 5: "narrow_256ch_n4096",
-            4: f"{storage}_256ch_n256"}[cfg] + ("_gemm" if engine == "gemm" else "") + ("_real" if real else "")
+def workload_key(cfg: int, storage: str, engine: str, real: bool = False, flags: int = 0) -> str:
+    return ({2: "fp32_64ch_n1024", 3: "batched_512ch_mixed", 5: "narrow_256ch_n4096",
+             4: f"{storage}_256ch_n256"}[cfg] + ("_gemm" if engine == "gemm" else "") + ("_real" if real else "")
+            + ("_noprune" if flags & 1 else ""))
 
 
 def oracle_input(w, ci: int, dtype: str):
@@ -310,7 +311,7 @@ def main():
     total = w.total_samples()
     bytes_per_sample = 16 if dtype == "c64" else 8
     achieved = total * bytes_per_sample / (kernel_ms * 1e-3) / 1e9
-    key = workload_key(args.config, dtype, args.engine, args.real)
+    key = workload_key(args.config, dtype, args.engine, args.real, args.flags)
     kernel = "ols_gemm" if args.engine == "gemm" else "ols_fft"
     traffic = traffic_from_profile(kernel, key, args.engine)
 
