@@ -469,7 +469,8 @@ def test_config2_full_size_sampled():
     dbs += check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128),
                          channels=range(2, 63, 5), n_random=1)
     say("config2 dB max/median", max(dbs), float(np.median(dbs)))
-    check_whole_channel(w, ys, 17, wl.channel_samples(w, 17, dtype=np.complex64).astype(np.complex128))
+    for ci in (17, 40):
+        check_whole_channel(w, ys, ci, wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128))
     plan.close()
 
 
@@ -499,6 +500,10 @@ def test_config4_full_size_sampled(storage, bound):
         dbs = check_sampled(w, ys32, lambda ci: harness.storage_to_c128(xs[ci]), channels=chans, n_random=8,
                             tol=FP32_DB if engine == "fft" else GEMM_COMPUTE_DB,
                             elem=ELEM_FP32 if engine == "fft" else ELEM_GEMM)
+        ci = 100 if engine == "fft" else 200
+        check_whole_channel(w, ys32, ci, harness.storage_to_c128(xs[ci]),
+                            tol=FP32_DB if engine == "fft" else GEMM_COMPUTE_DB,
+                            elem=ELEM_FP32 if engine == "fft" else ELEM_GEMM)
         say("config4", storage, engine, "compute-only dB max/median", max(dbs), float(np.median(dbs)))
         del ys32
         torch.cuda.empty_cache()
@@ -518,6 +523,10 @@ def test_config3_full_size_sampled():
     dbs = check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128),
                         channels=chans, n_random=3)
     say("config3 dB max/median", max(dbs), float(np.median(dbs)))
+    longest = int(np.argmax([c.length for c in w.channels]))
+    shortest = int(np.argmin([c.length for c in w.channels]))
+    for ci in (longest, shortest):
+        check_whole_channel(w, ys, ci, wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128))
     plan.close()
 
 
@@ -534,7 +543,8 @@ def test_config5_full_size_sampled():
     dbs += check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128),
                          channels=range(3, 255, 21), n_random=2)
     say("config5 dB max/median", max(dbs), float(np.median(dbs)))
-    check_whole_channel(w, ys, 200, wl.channel_samples(w, 200, dtype=np.complex64).astype(np.complex128))
+    for ci in (200, 7):
+        check_whole_channel(w, ys, ci, wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128))
     plan.close()
     del xs, ys
     torch.cuda.empty_cache()
