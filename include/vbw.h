@@ -151,8 +151,10 @@ vbw_status vbw_set_bandwidth(vbw_plan_t plan, int32_t channel, int32_t k1,
  * VBW_Q_N_VARIANTS)); the autotuner then keeps it.  Variant 0 is the default
  * shape: one persistent launch per DFT size at full residency with pruning
  * as the flags allow; the others change the resident workgroups per CU, the
- * grid (twice the resident count: shorter ranges per workgroup), pruning, or
- * use one launch of the kernel that dispatches on N (plans that mix N).  All
+ * grid (twice the resident count: shorter ranges per workgroup), pruning, the
+ * order of the work (chunks dealt to the workgroups in turn instead of one
+ * range each), or use one launch of the kernel that dispatches on N (plans
+ * that mix N).  All
  * variants compute the same result (Sec. II; only the schedule changes).
  * Errors: VBW_EINVAL (NULL plan, variant out of range); VBW_EUNSUPPORTED for
  * a VBW_HOST_ONLY plan. */

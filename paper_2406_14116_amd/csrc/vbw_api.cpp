@@ -157,6 +157,8 @@ struct vbw_plan_s {
         int grid_mult;   // workgroups per launch, in units of the resident count
         int prune;
         bool dispatch;   // one launch of the kernel that dispatches on N
+        int stride = 0;  // 0: a contiguous range per workgroup; k: chunks of k
+                         // tiles dealt to the workgroups in turn
     };
     std::vector<Shape> shapes;
     std::vector<std::vector<LaunchGroup>> variants;
@@ -324,6 +326,36 @@ int partition_items(vbw_plan_s *p, size_t b, size_t e, int n_wg, bool spans, boo
     return off;
 }
 
+// Chunks of `chunk` consecutive tiles of [b, e), dealt to the n_wg workgroups
+// in turn (chunk j to workgroup j mod n_wg): at any time the workgroups work
+// through one region of memory together, as a strided copy does, instead of
+// each walking its own range.  Tiles of one channel inside a chunk merge into
+// one span.  Appends like partition_items; returns the offset of the
+// boundaries.
+int partition_strided(vbw_plan_s *p, size_t b, size_t e, int n_wg, int chunk) {
+    const size_t n_chunks = (e - b + size_t(chunk) - 1) / size_t(chunk);
+    const int off = int(p->wg_begin.size());
+    for (int w = 0; w < n_wg; ++w) {
+        p->wg_begin.push_back(int32_t(p->work.size()));
+        for (size_t c = size_t(w); c < n_chunks; c += size_t(n_wg)) {
+            const size_t t0 = b + c * size_t(chunk), t1 = std::min(e, t0 + size_t(chunk));
+            for (size_t t = t0; t < t1; ++t) {
+                const WorkItem &it = p->items[t];
+                if (t > t0) {
+                    WorkItem &last = p->work.back();
+                    if (last.channel == it.channel && last.first_block + last.n_blocks == it.first_block) {
+                        last.n_blocks += it.n_blocks;
+                        continue;
+                    }
+                }
+                p->work.push_back(it);
+            }
+        }
+    }
+    p->wg_begin.push_back(int32_t(p->work.size()));
+    return off;
+}
+
 vbw::Storage storage_of(int32_t dtype) {
     return dtype == VBW_CF16    ? vbw::Storage::F16
            : dtype == VBW_CBF16 ? vbw::Storage::BF16
@@ -397,7 +429,9 @@ void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
             const int lg = p->items[g.first].log2n;
             const int n_wg = wg_count(g.second - g.first, size_t(n_cu) * per_cu(lg, sh.occ_drop) * sh.grid_mult,
                                       p->max_wg);
-            v.push_back({gemm ? -1 : lg, partition_items(p, g.first, g.second, n_wg, true), n_wg, sh.prune});
+            const int o = sh.stride ? partition_strided(p, g.first, g.second, n_wg, sh.stride)
+                                    : partition_items(p, g.first, g.second, n_wg, true);
+            v.push_back({gemm ? -1 : lg, o, n_wg, sh.prune});
         }
         return v;
     };
@@ -414,6 +448,7 @@ void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
                 if (drop != 0 || grid != 1 || prune != prune_max) add({drop, grid, prune, false});
     if (!gemm && groups.size() > 1)
         for (int drop = 0; drop < 2; ++drop) add({drop, 1, prune_max, true});
+    for (int chunk : {2, 8}) add({0, 1, prune_max, false, chunk});
 }
 
 // The variant that takes, for N group g, the launch of per-N variant choice[g].

@@ -319,7 +319,8 @@ def test_graph_replay_matches_eager():
 def test_every_launch_variant_and_the_autotuner():
     """Every launch variant the autotuner searches for a mixed-N plan (per-N
     launches at two occupancies, two grid sizes, pruned or not; one launch
-    dispatching on N at two occupancies) against the oracle, fixed one at a
+    dispatching on N at two occupancies; chunks dealt to the workgroups in
+    turn, two chunk sizes) against the oracle, fixed one at a
     time with vbw_plan_set_variant, eagerly and replayed from a graph; then
     the autotuner keeps one of them (possibly a per-N combination)."""
     rng = np.random.default_rng(6)
@@ -332,7 +333,7 @@ def test_every_launch_variant_and_the_autotuner():
            for x, s in zip(xs, specs)]
     p = vbw.Plan(chans, pool)
     n_var = p.query(vbw.Q_N_VARIANTS)
-    assert n_var == 10
+    assert n_var == 12
     p.close()
     stream = torch.cuda.Stream()
     for k in range(n_var):
@@ -623,9 +624,9 @@ def test_gemm_engine_edge_shapes_every_block(storage):
     x_stored = [harness.storage_to_c128(x) for x in xs]
     refs = [ols.channel_hfso(x, n, hop, v_sets[(n, lv)], [(0, k1)] + sched.get(ci, []))
             for ci, (x, (hop, lv, k1, L)) in enumerate(zip(x_stored, specs))]
-    for variant in range(4):
+    for variant in range(6):
         plan = vbw.Plan(chans, pool, dtype=storage, engine="gemm", flags=vbw.F32_OUT)
-        assert plan.query(vbw.Q_N_VARIANTS) == 4
+        assert plan.query(vbw.Q_N_VARIANTS) == 6
         plan.set_variant(variant)
         assert plan.query(vbw.Q_VARIANT) == variant
         for ci, entries in sched.items():
@@ -1016,7 +1017,7 @@ def test_tuning_cache_is_written_and_read(tmp_path):
         if want_variant is not None:
             assert got == want_variant
         else:                 # the combination is added as the last variant
-            assert got == p2.query(vbw.Q_N_VARIANTS) - 1 == 10
+            assert got == p2.query(vbw.Q_N_VARIANTS) - 1 == 12
         ys = [torch.empty_like(x) for x in xs]
         run_plan(p2, xs, ys)
         assert p2.query(vbw.Q_VARIANT) == got
