@@ -284,6 +284,46 @@ def test_deterministic_bitwise():
         assert np.array_equal(ya.view(np.float64), yb.view(np.float64))
 
 
+def test_bitwise_identical_across_launch_schedules():
+    """Blocks are independent (Sec. II) and a block's arithmetic does not
+    depend on which workgroup or launch filters it: every launch variant of a
+    plan without pruning gives the same bits (per-N launches at any occupancy
+    and grid, the single launch over every N, strided chunk order), with band
+    changes, ragged lengths and mixed N.  (Pruning is decided per wave, so a
+    wave that holds blocks on both sides of a band change may prune one and
+    not another depending on the schedule: same result to rounding, not the
+    same bits; the other variants are checked against the oracle elsewhere.)"""
+    rng = np.random.default_rng(21)
+    specs = [(256, 192, 8, 20, 90001, (256, 8)), (1024, 768, 16, 100, 300003, (1024, 16)),
+             (2048, 1536, 16, 300, 200000, (2048, 16)), (512, 384, 8, 50, 50000, (512, 8)),
+             (64, 48, 4, 6, 30000, (64, 4))]
+    sched = {0: [(7, 60), (200, 10)], 1: [(100, 30)], 4: [(9, 20)]}
+    v_sets = v_for({s[5] for s in specs})
+    chans, pool = channels_from(specs, v_sets)
+    xs = [torch.from_numpy(crandn(rng, s[4])).cuda() for s in specs]
+    ref = None
+    p = vbw.Plan(chans, pool, flags=vbw.NO_PRUNE)
+    n_var = p.query(vbw.Q_N_VARIANTS)
+    p.close()
+    assert n_var == 8
+    for k in range(n_var):
+        p = vbw.Plan(chans, pool, flags=vbw.NO_PRUNE)
+        for ci, entries in sched.items():
+            for frm, k1 in entries:
+                p.set_bandwidth(ci, k1, frm)
+        p.set_variant(k)
+        ys = [torch.full_like(x, complex(np.nan, np.nan)) for x in xs]
+        run_plan(p, xs, ys)
+        p.close()
+        got = [y.cpu().numpy().view(np.uint64) for y in ys]
+        if ref is None:
+            ref = got
+            continue
+        for ci, (a, b) in enumerate(zip(ref, got)):
+            assert np.array_equal(a, b), (k, ci)
+    say("launch variants bitwise identical:", n_var)
+
+
 def test_graph_replay_matches_eager():
     rng = np.random.default_rng(4)
     specs = [(1024, 768, 16, 60, 200000, (1024, 16)), (2048, 1536, 8, 300, 100000, (2048, 8))]
