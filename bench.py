@@ -293,20 +293,24 @@ def main():
         plan.filter(xs, ys, stream)
     torch.cuda.synchronize()
 
-    # one pair of events around the K steps on the plan's stream: the launches
-    # run back to back, and the mean launch time is the span over K
-    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    # a pair of events around every call on the plan's stream: the mean of the
+    # pairs is the launch duration (the span from the first to the last event
+    # adds the dispatch gaps between consecutive launches, reported beside it)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record(stream)
-    for _ in range(args.steps):
+    for a, b in ev:
+        a.record(stream)
         plan.filter(xs, ys, stream)
-    ev[1].record(stream)
+        b.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kernel_ms = ev[0].elapsed_time(ev[1]) / args.steps
-    log(f"bench: {ms_per_step:.3f} ms/step wall, {kernel_ms:.3f} ms/launch (events)")
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    span_ms = ev[0][0].elapsed_time(ev[-1][1]) / args.steps
+    log(f"bench: {ms_per_step:.3f} ms/step wall, {kernel_ms:.3f} ms/launch (events), "
+        f"{span_ms:.3f} ms/launch over the span")
 
     total = w.total_samples()
     bytes_per_sample = 16 if dtype == "c64" else 8
@@ -347,7 +351,7 @@ def main():
                    "description": w.description},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel_ms": kernel_ms,
+                     "kernel_ms": kernel_ms, "span_ms_per_launch": span_ms,
                      "algorithmic_bytes": total * bytes_per_sample,
                      "copy_gbs": copy, "frac_of_copy": achieved / max(copy.values())},
         "cpu_baseline": cpu,

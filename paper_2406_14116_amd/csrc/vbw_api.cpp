@@ -143,9 +143,9 @@ struct vbw_plan_s {
     std::vector<int32_t> wg_begin;   // concatenated per-launch workgroup ranges of `work`
     // Launch variants: each is a list of persistent launches (one per N group,
     // or one launch of the kernel that dispatches on N), each with its own
-    // workgroup count, item partition and pruning switch.  The first ones
-    // apply one shape to every group (shape_params); after autotuning a last
-    // one may combine, per N group, the fastest of the per-N shapes.
+    // workgroup count, item partition and pruning switch.  Variant i applies
+    // shapes[i] to every group; after autotuning a last one may combine, per
+    // N group, the fastest of the per-N shapes (composite).
     struct LaunchGroup {
         int log2n;       // 0: kernel that dispatches on N; -1: matrix-core kernel
         int wg_off;      // offset of this launch's range table in wg_begin
@@ -369,8 +369,9 @@ vbw::Storage storage_of(int32_t dtype) {
 //   resident workgroups per CU: the kernel's maximum, or one fewer;
 //   grid: the resident count, or twice it (shorter ranges, finer balance);
 //   pruning: on (when the flags allow it) or off;
-// and, for plans that mix N, one launch of the kernel that dispatches on N at
-// either occupancy.
+// then, for FFT-engine plans that mix N, one launch of the kernel that
+// dispatches on N at either occupancy; last, the default shape with chunks of
+// 2 or 8 tiles dealt to the workgroups in turn (partition_strided).
 void build_variants(vbw_plan_s *p, int n_cu, bool only_default = false) {
     p->variants.clear();
     p->shapes.clear();
