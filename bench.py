@@ -42,18 +42,24 @@ def kernel_hash(engine: str) -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(kernel: str, workload_key: str, engine: str):
-    """HBM bytes per launch measured by rocprofv3 counters, if the committed
-    summary was taken on the current kernel source."""
+def counters_from_profile(kernel: str, workload_key: str, engine: str):
+    """HBM bytes per launch and the VALU / MFMA busy fractions measured by
+    rocprofv3 counters, if the committed summary was taken on the current
+    kernel source: (traffic or None, {"valu_busy": f, "mfma_busy": f})."""
     path = os.path.join(PROFILE_DIR, f"{kernel}_{workload_key}_pmc.md")
     if not os.path.exists(path):
-        return None
+        return None, {}
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel_hash(engine):
+        return None, {}
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != kernel_hash(engine):
-        return None
-    return float(t.group(1))
+    busy = {}
+    for name in ("VALU", "MFMA"):
+        b = re.search(name + r" busy = .* = ([0-9.]+)%", text)
+        if b:
+            busy[name.lower() + "_busy"] = float(b.group(1)) / 100
+    return (float(t.group(1)) if t else None), busy
 
 
 def make_workload(cfg: int, storage: str, real: bool = False):
@@ -307,7 +313,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    pairs = [a.elapsed_time(b) for a, b in ev]
+    kernel_ms = float(np.mean(pairs))
     span_ms = ev[0][0].elapsed_time(ev[-1][1]) / args.steps
     log(f"bench: {ms_per_step:.3f} ms/step wall, {kernel_ms:.3f} ms/launch (events), "
         f"{span_ms:.3f} ms/launch over the span")
@@ -317,7 +324,7 @@ def main():
     achieved = total * bytes_per_sample / (kernel_ms * 1e-3) / 1e9
     key = workload_key(args.config, dtype, args.engine, args.real, args.flags)
     kernel = "ols_gemm" if args.engine == "gemm" else "ols_fft"
-    traffic = traffic_from_profile(kernel, key, args.engine)
+    traffic, busy = counters_from_profile(kernel, key, args.engine)
 
     copy = copy_bandwidth(total * bytes_per_sample // 2)
     log(f"bench: plain copy of the same bytes: {copy}")
@@ -350,8 +357,9 @@ def main():
                    "variant": plan.query(vbw.Q_VARIANT), "variants_searched": plan.query(vbw.Q_N_VARIANTS),
                    "description": w.description},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel_ms": kernel_ms, "span_ms_per_launch": span_ms,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, **busy,
+                     "kernel_ms": kernel_ms, "kernel_ms_median": float(np.median(pairs)),
+                     "span_ms_per_launch": span_ms,
                      "algorithmic_bytes": total * bytes_per_sample,
                      "copy_gbs": copy, "frac_of_copy": achieved / max(copy.values())},
         "cpu_baseline": cpu,
