@@ -9,9 +9,11 @@
 //   B (32 x 16): lane (g, c) holds column c, contraction entries 8g .. 8g+7
 //   D (16 x 16): lane (g, c) holds rows 4g .. 4g+3 of column c
 // A complex contraction over 16 terms puts term t(g, j) (j < 4) of lane group
-// g at entries 8g + j (real parts) and 8g + 4 + j (imaginary parts); only
-// the pairing of entries between A and B matters, so each stage may order
-// its 16 terms as it likes, provided both operands agree.
+// g at entries 8g + j (real parts) and 8g + 4 + j (imaginary parts), except in
+// S1, whose entries 8g + 2j, 8g + 2j + 1 hold the real and imaginary part as
+// the samples are stored; only the pairing of entries between A and B
+// matters, so each stage may order its 16 terms as it likes, provided both
+// operands agree.
 //
 // The four products of one block (W[a][b] = w16^{ab}, w16 = exp(-j 2 pi/16)):
 //   S1  D1[n2][k1] = sum_n1 x[n1][n2] W[n1][k1]      A = input, B = W

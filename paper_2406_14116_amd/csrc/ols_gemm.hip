@@ -54,11 +54,28 @@ constexpr int kOutOfRange = int(0x80000000u);   // as an unsigned offset: past e
 constexpr int kVCapG = kGemmN / 2;
 constexpr int kTarget = 6;                       // block maximum scaled into [2^6, 2^7)
 
+constexpr int64_t kMaxRecords = 0x7ffff000;
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int64_t bytes) {
-    const int64_t cap = 0x7ffff000;
-    const int n = int(bytes <= 0 ? 0 : (bytes < cap ? bytes : cap));
+    const int n = int(bytes <= 0 ? 0 : (bytes < kMaxRecords ? bytes : kMaxRecords));
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, n, kBufFlags);
 }
+
+// Bytes from block q's first sample to the channel end, min(b0 - q step,
+// kMaxRecords), in 32-bit scalar arithmetic (the scalar unit has no 64-bit
+// ordered compare): the first `sat` blocks have more than kMaxRecords left,
+// and below it the low 32 bits of b0 - q step are exact.  Valid for blocks
+// that have samples left.
+struct BytesLeft {
+    uint32_t b0, step;
+    int sat;
+    __device__ __forceinline__ BytesLeft(int64_t bytes0, uint32_t step_) : b0(uint32_t(bytes0)), step(step_), sat(0) {
+        if (bytes0 > kMaxRecords) sat = int((bytes0 - kMaxRecords + step - 1) / step);
+    }
+    __device__ __forceinline__ int at(int q) const {
+        return q < sat ? int(kMaxRecords) : int(b0 - uint32_t(q) * step);
+    }
+};
 
 template <typename T> __device__ __forceinline__ T ld_uniform(const T *p, int i) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -83,12 +100,23 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {  // RN, one v_
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf2v));
 }
 // FP16 pair RN(v0 - hi0), RN(v1 - hi1) for h = (hi0, hi1): one mixed-precision
-// multiply-add per value reads the FP16 half and rounds straight to FP16
+// multiply-add per value reads the FP16 half and rounds straight to FP16.
+// Its operands are always results of ordinary vector instructions, never a
+// matrix-core result read directly: the compiler inserts the wait states such
+// a read needs before its own instructions, not before inline assembly.
 __device__ __forceinline__ uint32_t residual_pair(uint32_t h, float v0, float v1) {
     uint32_t l;
     asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=&v"(l) : "v"(h), "v"(v0));
     asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(l) : "v"(h), "v"(v1));
     return l;
+}
+// After the residuals of an operand: two wait states before any instruction
+// reads them.  A matrix-core read of a register a vector instruction has just
+// written needs them; the compiler counts them for its own instructions only,
+// and this statement, which takes the four registers as inputs and outputs,
+// comes after every residual and before every use.
+__device__ __forceinline__ void residuals_settle(u4v &lo) {
+    asm volatile("s_nop 1" : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]));
 }
 // operand (re[0..3] | im[0..3]) as hi + lo
 __device__ __forceinline__ Split split(f4 re, f4 im) {
@@ -101,9 +129,21 @@ __device__ __forceinline__ Split split(f4 re, f4 im) {
     lo[1] = residual_pair(hi[1], re[2], re[3]);
     lo[2] = residual_pair(hi[2], im[0], im[1]);
     lo[3] = residual_pair(hi[3], im[2], im[3]);
+    residuals_settle(lo);
     return {__builtin_bit_cast(h8, hi), __builtin_bit_cast(h8, lo)};
 }
-
+// operand (a0, b0, a1, b1, ..., a3, b3) as hi + lo: S1's DFT-matrix operand,
+// whose contraction entries pair with the samples as stored, (re, im) each
+__device__ __forceinline__ Split split_interleaved(f4 a, f4 b) {
+    u4v hi, lo;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        hi[j] = pack_f16(a[j], b[j]);
+        lo[j] = residual_pair(hi[j], a[j], b[j]);
+    }
+    residuals_settle(lo);
+    return {__builtin_bit_cast(h8, hi), __builtin_bit_cast(h8, lo)};
+}
 // Real product of split operands: P*Q ~ Phi*Qhi + Plo*Qhi + Phi*Qlo.
 __device__ __forceinline__ f4 mm3(const Split &p, const Split &q) {
     const f4 z = {0.f, 0.f, 0.f, 0.f};
@@ -124,7 +164,7 @@ __device__ __forceinline__ f4 mm2(h8 p, const Split &q) {
 // sum Y conj W = conj(sum conj(Y) W), with the signs folded into the
 // neighbouring multiplies.
 struct GemmConst {
-    Split s1r, s1i;   // S1 (B = W):      [Re W | -Im W], [Im W | Re W]
+    Split s1r, s1i;   // S1 (B = W):      (Re W, -Im W), (Im W, Re W) interleaved
     Split s2r, s2i;   // S2 (A = W) and S3 (B = W, conjugated data)
     Split s4r, s4i;   // S4 (A = conj W): [Re W |  Im W], [-Im W | Re W]
     float2 tw[4];
@@ -144,8 +184,8 @@ __device__ __forceinline__ void load_consts(GemmConst &k, const float2 *__restri
     const int g = lane >> 4, c = lane & 15;
     f4 wr, wi;
     w_entries<s1_w>(tw4096, g, c, wr, wi);
-    k.s1r = split(wr, -wi);
-    k.s1i = split(wi, wr);
+    k.s1r = split_interleaved(wr, -wi);
+    k.s1i = split_interleaved(wi, wr);
     w_entries<s2_w>(tw4096, g, c, wr, wi);
     k.s2r = split(wr, -wi);
     k.s2i = split(wi, wr);
@@ -157,16 +197,17 @@ __device__ __forceinline__ void load_consts(GemmConst &k, const float2 *__restri
 }
 
 // ------------------------------------------------------------ block scale
-// Largest of a wave's unsigned values, in every lane (rows of 16 lanes by
-// DPP shifts, then the four row results).
+// Largest of a wave's unsigned values, as a wave-uniform value: row DPP
+// shifts leave each row's maximum in its lane 15, the two row broadcasts
+// carry it on to lane 63.
 __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
     x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x111, 0xf, 0xf, true)));   // row_shr:1
     x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x112, 0xf, 0xf, true)));   // row_shr:2
     x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x114, 0xf, 0xf, true)));   // row_shr:4
     x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x118, 0xf, 0xf, true)));   // row_shr:8
-    const uint32_t a = __builtin_amdgcn_readlane(x, 15), b = __builtin_amdgcn_readlane(x, 31);
-    const uint32_t c = __builtin_amdgcn_readlane(x, 47), d = __builtin_amdgcn_readlane(x, 63);
-    return max(max(a, b), max(c, d));
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x142, 0xa, 0xf, false)));  // row_bcast:15, rows 1, 3
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x143, 0xc, 0xf, false)));  // row_bcast:31, rows 2, 3
+    return __builtin_amdgcn_readlane(x, 63);
 }
 
 // Largest |re|, |im| of the block's 16-bit samples as a bit pattern with the
@@ -202,46 +243,52 @@ struct CF4 {
     f4 re, im;
 };
 
+// Twiddles w256^{n2 k1} times the block scale 2^sh (FP16 input takes its
+// scale there), recomputed only when sh changes from one block to the next.
+struct ScaledTw {
+    float2 w[4];
+    int sh = INT32_MIN;
+};
+
 // One OLS block of N = 256 by one wave.  u[j]: the (re, im) 16-bit pair of
 // sample 16 in_row(g, j) + c; hf[r]: H_R / 16 of the bin in slot r; tgt: the
-// exponent the block maximum is scaled to; oofs[r]: byte offset of slot r's
-// output sample from the block's first output (kOutOfRange: not kept).
+// exponent the block maximum is scaled to; yr: the output from the block's
+// first kept sample on, oofs[r]: byte offset of slot r's sample in it
+// (kOutOfRange: not kept).
 template <Storage S, bool F32OUT>
 __device__ __forceinline__ void gemm_block(const GemmConst &K, const uint32_t (&u)[4], const float (&hf)[4], int tgt,
-                                           __amdgpu_buffer_rsrc_t yr, int obyte, const int (&oofs)[4]) {
-    const uint32_t mb = block_max_bits(u);
+                                           __amdgpu_buffer_rsrc_t yr, const int (&oofs)[4], ScaledTw &tws) {
+    const uint32_t mb = block_max_bits(u);                  // wave-uniform
     const int e = mb ? exponent_of<S>(mb) : tgt;
     const int sh = tgt - e;            // block scale 2^sh
     const int dsc = e - tgt - 4;       // at the store: 2^-sh and the other 1/16 of 1/N
 
-    // S1 operand: the samples (FP16 as stored; BF16 scaled, then rounded to FP16)
+    // S1 operand: the samples as stored, (re, im) interleaved (FP16 as is;
+    // BF16 scaled, then rounded to FP16)
     u4v xa;
     if constexpr (S == Storage::F16) {
-        xa[0] = __builtin_amdgcn_perm(u[1], u[0], 0x05040100u);   // re0 re1
-        xa[1] = __builtin_amdgcn_perm(u[3], u[2], 0x05040100u);   // re2 re3
-        xa[2] = __builtin_amdgcn_perm(u[1], u[0], 0x07060302u);   // im0 im1
-        xa[3] = __builtin_amdgcn_perm(u[3], u[2], 0x07060302u);   // im2 im3
-    } else {
-        float re[4], im[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            re[j] = __builtin_ldexpf(__uint_as_float(u[j] << 16), sh);
-            im[j] = __builtin_ldexpf(__uint_as_float(u[j] & 0xffff0000u), sh);
+        for (int j = 0; j < 4; ++j) xa[j] = u[j];
+        if (sh != tws.sh) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                tws.w[r] = make_float2(__builtin_ldexpf(K.tw[r].x, sh), __builtin_ldexpf(K.tw[r].y, sh));
+            tws.sh = sh;
         }
-        xa[0] = pack_f16(re[0], re[1]);
-        xa[1] = pack_f16(re[2], re[3]);
-        xa[2] = pack_f16(im[0], im[1]);
-        xa[3] = pack_f16(im[2], im[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            xa[j] = pack_f16(__builtin_ldexpf(__uint_as_float(u[j] << 16), sh),
+                             __builtin_ldexpf(__uint_as_float(u[j] & 0xffff0000u), sh));
     }
     const h8 x = __builtin_bit_cast(h8, xa);
     CF4 d;
     d.re = mm2(x, K.s1r);
     d.im = mm2(x, K.s1i);
-    // twiddle w256^{n2 k1}; FP16 input takes its block scale here
+    // twiddle w256^{n2 k1}
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        float2 w = K.tw[r];
-        if constexpr (S == Storage::F16) w = make_float2(__builtin_ldexpf(w.x, sh), __builtin_ldexpf(w.y, sh));
+        const float2 w = S == Storage::F16 ? tws.w[r] : K.tw[r];
         const float a = d.re[r], b = d.im[r];
         d.re[r] = a * w.x - b * w.y;
         d.im[r] = a * w.y + b * w.x;
@@ -282,7 +329,7 @@ __device__ __forceinline__ void gemm_block(const GemmConst &K, const uint32_t (&
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        gstore<F32OUT, S>(yr, obyte + oofs[r], __builtin_ldexpf(q.re[r], dsc), __builtin_ldexpf(q.im[r], dsc));
+        gstore<F32OUT, S>(yr, oofs[r], __builtin_ldexpf(q.re[r], dsc), __builtin_ldexpf(q.im[r], dsc));
 }
 
 // H_R / 16 of this lane's four bins k = c + 16 (4 g + r) for the edge k1
@@ -306,6 +353,9 @@ __device__ __forceinline__ void h_factors(float (&hf)[4], int lane, int k1, int 
 // (w+1) n / 4) of each span's n blocks.  With M = 192 (CARRY) a block's
 // slot 0 is the previous block's slot 3, so each later block loads 3 of its
 // 4 slots; the next block's loads are in flight during the current block.
+// Every block gets buffer resources that start at its own first input
+// sample and first output sample (scalar arithmetic), so the lanes' offsets
+// stay fixed from block to block.
 template <Storage S, bool F32OUT, bool CARRY>
 __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp, const ChannelDev &cd,
                                          const GemmConst &K, const float *vl, int tgt, int lane, int wave) {
@@ -316,14 +366,14 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
     const int lo = (wave * n) / kWaves;
     const int cnt = ((wave + 1) * n) / kWaves - lo;
     if (cnt <= 0) return;
-    const int64_t seg0 = int64_t(sp.first_block) * hop - (kGemmN - hop);
-    const int64_t clip = seg0 > 0 ? seg0 : 0;
-    const auto xr = make_rsrc(static_cast<const char *>(ld_uniform(A.x, sp.channel)) + clip * 4, (cd.len - clip) * 4);
-    const int64_t ob = int64_t(sp.first_block) * hop;
-    const auto yr = make_rsrc(static_cast<char *>(ld_uniform(A.y, sp.channel)) + ob * EO, (cd.len - ob) * EO);
-    const int base0 = int(seg0 - clip) + lo * hop;      // segment start of the wave's first block (may be < 0)
-    // per-lane byte offsets: input slot j from the segment start, output slot r
-    // from the block's first kept sample (kOutOfRange where not kept)
+    tgt = __builtin_amdgcn_readfirstlane(tgt);                 // wave-uniform: scalar block scales
+    const char *const xb = static_cast<const char *>(ld_uniform(A.x, sp.channel));
+    char *const yb = static_cast<char *>(ld_uniform(A.y, sp.channel));
+    const int64_t len = cd.len;
+    const int64_t m0 = int64_t(sp.first_block) + lo;         // the wave's first block
+    const int64_t seg0 = m0 * hop - (kGemmN - hop);          // its first input sample (may be < 0)
+    // per-lane byte offsets: input slot j from the block's first input sample,
+    // output slot r from its first kept output sample (kOutOfRange: not kept)
     const int dly = (kGemmN - hop) >> 1;
     int iofs[4], oofs[4];
 #pragma unroll
@@ -334,49 +384,76 @@ __device__ __forceinline__ void run_span(const LaunchArgs &A, const WorkItem &sp
         oofs[r] = unsigned(jj) < unsigned(hop) ? EO * jj : kOutOfRange;
     }
     // band schedule: entry in force at the wave's first block (binary search),
-    // then one step forward whenever a block reaches the next entry
-    const int64_t m0 = int64_t(sp.first_block) + lo;
+    // then one step forward whenever a block reaches the next entry (nq: that
+    // entry's block, relative to m0)
     int ea = 0, eb = cd.sched_count;                 // sched[ea].from_block <= m0 < sched[eb].from_block
     while (eb - ea > 1) {
         const int mid = (ea + eb) >> 1;
         if (ld_uniform(A.sched, cd.sched_begin + mid).from_block <= m0) ea = mid;
         else eb = mid;
     }
+    auto next_rel = [&](int e) {
+        if (e + 1 >= cd.sched_count) return INT32_MAX;
+        const int64_t d = ld_uniform(A.sched, cd.sched_begin + e + 1).from_block - m0;
+        return d < INT32_MAX ? int(d) : INT32_MAX;
+    };
     int k1 = ld_uniform(A.sched, cd.sched_begin + ea).k1;
-    int64_t next_from = ea + 1 < cd.sched_count ? ld_uniform(A.sched, cd.sched_begin + ea + 1).from_block : INT64_MAX;
+    int nq = next_rel(ea);
     int k1c = -1;
     float hf[4];
+    ScaledTw tws;
 
-    uint32_t u[4], un[4];
-    // a load at a negative offset is past the resource's end as an unsigned
-    // offset and reads 0 (the zero history before sample 0)
-    __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) u[j] = __builtin_amdgcn_raw_buffer_load_b32(xr, 4 * base0 + iofs[j], 0, kNT);
-    __builtin_amdgcn_s_setprio(0);
-    for (int q = 0; q < cnt; ++q) {
-        // next block's loads (past the end after the last block, so that every
-        // step issues the same number)
-        const int nb4 = q + 1 < cnt ? 4 * (base0 + (q + 1) * hop) : kOutOfRange;
+    // Loads of block q's slots J0..3 (q == cnt: none are needed; they read 0
+    // from an empty resource, so that every step issues the same loads).  The
+    // blocks before qpos start before sample 0: they read from the channel
+    // start at a negative offset, past the resource's end as an unsigned
+    // offset, which gives 0, the zero history.
+    const int qpos = seg0 >= 0 ? 0 : int((-seg0 + hop - 1) / hop);
+    const BytesLeft in_left(4 * (len - seg0), 4u * uint32_t(hop));
+    auto issue = [&](uint32_t(&dst)[4], int q, int j0) {
         __builtin_amdgcn_s_setprio(1);
+        if (q < cnt && q >= qpos) {
+            const auto r = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char *>(xb + 4 * (seg0 + int64_t(q) * hop)), 0, in_left.at(q), kBufFlags);
 #pragma unroll
-        for (int j = CARRY ? 1 : 0; j < 4; ++j) un[j] = __builtin_amdgcn_raw_buffer_load_b32(xr, nb4 + iofs[j], 0, kNT);
+            for (int j = j0; j < 4; ++j) dst[j] = __builtin_amdgcn_raw_buffer_load_b32(r, iofs[j], 0, kNT);
+        } else {
+            const auto r = make_rsrc(xb, q < cnt ? 4 * len : 0);
+            const int b = q < cnt ? 4 * int(seg0 + int64_t(q) * hop) : 0;
+#pragma unroll
+            for (int j = j0; j < 4; ++j) dst[j] = __builtin_amdgcn_raw_buffer_load_b32(r, b + iofs[j], 0, kNT);
+        }
         __builtin_amdgcn_s_setprio(0);
-        const int64_t m = m0 + q;
-        if (m >= next_from) {
+    };
+    const BytesLeft out_left(int64_t(EO) * (len - m0 * hop), uint32_t(EO * hop));
+    auto block = [&](const uint32_t(&u)[4], int q) {
+        if (q >= nq) {
             ++ea;
             k1 = ld_uniform(A.sched, cd.sched_begin + ea).k1;
-            next_from = ea + 1 < cd.sched_count ? ld_uniform(A.sched, cd.sched_begin + ea + 1).from_block : INT64_MAX;
+            nq = next_rel(ea);
         }
         if (k1 != k1c) {
             h_factors(hf, lane, k1, cd.lv, vl);
             k1c = k1;
         }
-        gemm_block<S, F32OUT>(K, u, hf, tgt, yr, EO * (lo + q) * hop, oofs);
-        if constexpr (CARRY) un[0] = u[3];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) u[j] = un[j];
+        const auto yr = __builtin_amdgcn_make_buffer_rsrc(yb + EO * (m0 + q) * hop, 0, out_left.at(q), kBufFlags);
+        gemm_block<S, F32OUT>(K, u, hf, tgt, yr, oofs, tws);         // the block's first kept output sample on
+    };
+
+    // two blocks per step, so that the loads alternate between two register
+    // sets instead of being copied from one to the other
+    uint32_t ua[4], ub[4];
+    issue(ua, 0, 0);
+    int q = 0;
+    for (; q + 1 < cnt; q += 2) {
+        issue(ub, q + 1, CARRY ? 1 : 0);
+        block(ua, q);
+        if constexpr (CARRY) ub[0] = ua[3];
+        issue(ua, q + 2, CARRY ? 1 : 0);
+        block(ub, q + 1);
+        if constexpr (CARRY) ua[0] = ub[3];
     }
+    if (q < cnt) block(ua, q);
 }
 
 template <Storage S, bool F32OUT>

