@@ -299,17 +299,27 @@ def main():
         plan.filter(xs, ys, stream)
     torch.cuda.synchronize()
 
-    # a pair of events around every call on the plan's stream: the mean of the
-    # pairs is the launch duration (the span from the first to the last event
-    # adds the dispatch gaps between consecutive launches, reported beside it)
+    # Launch duration: a pair of events per call that take the filter kernels'
+    # own start and end time (vbw_filter_timed); a graph-replayed plan gets a
+    # pair recorded on the stream around the call instead, which adds the
+    # launch latency.  The span from the first event to the last adds the
+    # dispatch gaps between consecutive calls and is reported beside it.
+    kernel_events = not (args.flags & vbw.GRAPH)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    if kernel_events:
+        for a, b in ev:            # create the events before they are handed to the library
+            a.record(stream)
+            b.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in ev:
-        a.record(stream)
-        plan.filter(xs, ys, stream)
-        b.record(stream)
+        if kernel_events:
+            plan.filter_timed(xs, ys, a, b, stream)
+        else:
+            a.record(stream)
+            plan.filter(xs, ys, stream)
+            b.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -360,6 +370,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, **busy,
                      "kernel_ms": kernel_ms, "kernel_ms_median": float(np.median(pairs)),
                      "span_ms_per_launch": span_ms,
+                     "launch_timing": "kernel start/end events (vbw_filter_timed)" if kernel_events
+                                      else "events on the stream around each graph launch",
                      "algorithmic_bytes": total * bytes_per_sample,
                      "copy_gbs": copy, "frac_of_copy": achieved / max(copy.values())},
         "cpu_baseline": cpu,

@@ -192,6 +192,20 @@ vbw_status vbw_plan_set_variant(vbw_plan_t plan, int32_t variant);
 vbw_status vbw_filter(vbw_plan_t plan, const void *const *x, void *const *y,
                       void *stream);
 
+/* vbw_filter, with the kernels' own duration: start_event and stop_event
+ * (hipEvent_t, created by the caller on the plan's device, timing enabled)
+ * take the start time of the call's first filter kernel and the end time of
+ * its last, as the GPU records them for the dispatch itself, so that
+ * hipEventElapsedTime(start, stop) excludes the queueing and launch latency
+ * that events recorded on the stream around the call include.  For
+ * measurement: the same work and results as vbw_filter.  A VBW_STREAM plan's
+ * state update, which follows the filter kernels, is outside the interval.
+ * Errors: as vbw_filter, plus VBW_EINVAL for a NULL event and
+ * VBW_EUNSUPPORTED for a VBW_GRAPH plan (its launches are replayed from a
+ * graph; time the graph launch with events on the stream instead). */
+vbw_status vbw_filter_timed(vbw_plan_t plan, const void *const *x, void *const *y,
+                            void *stream, void *start_event, void *stop_event);
+
 /* Restart every channel's stream of a VBW_STREAM plan (Sec. II framing):
  * zero history and block counters, stream-ordered on `stream` (a hipStream_t,
  * NULL: the null stream).  The next vbw_filter behaves like the plan's first.

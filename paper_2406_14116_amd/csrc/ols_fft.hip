@@ -29,6 +29,7 @@
 // Twiddles come from one float32 table w_4096^r (generated in float64 on the
 // host, rounded to nearest).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
@@ -782,20 +783,28 @@ void ols_fft_kernel(const LaunchArgs A) {
     }
 }
 
+// One dispatch; with events, through hipExtLaunchKernel, which records the
+// kernel's own start and end time in them.
+template <typename K>
+void dispatch(K kernel, dim3 grid, dim3 block, hipStream_t stream, hipEvent_t t0, hipEvent_t t1, const LaunchArgs &A) {
+    if (t0 || t1) hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, t0, t1, 0, A);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, stream, A);
+}
+
 template <Storage S, bool F32OUT>
-hipError_t launch_typed(const LaunchArgs &A, int log2n, hipStream_t stream) {
+hipError_t launch_typed(const LaunchArgs &A, int log2n, hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
     const dim3 grid(A.n_wg), block(kThreads);
     switch (log2n) {
-        case 0: hipLaunchKernelGGL((ols_fft_kernel<0, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 4: hipLaunchKernelGGL((ols_fft_kernel<4, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 5: hipLaunchKernelGGL((ols_fft_kernel<5, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 6: hipLaunchKernelGGL((ols_fft_kernel<6, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 7: hipLaunchKernelGGL((ols_fft_kernel<7, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 8: hipLaunchKernelGGL((ols_fft_kernel<8, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 9: hipLaunchKernelGGL((ols_fft_kernel<9, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 10: hipLaunchKernelGGL((ols_fft_kernel<10, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 11: hipLaunchKernelGGL((ols_fft_kernel<11, S, F32OUT>), grid, block, 0, stream, A); break;
-        case 12: hipLaunchKernelGGL((ols_fft_kernel<12, S, F32OUT>), grid, block, 0, stream, A); break;
+        case 0: dispatch(ols_fft_kernel<0, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 4: dispatch(ols_fft_kernel<4, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 5: dispatch(ols_fft_kernel<5, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 6: dispatch(ols_fft_kernel<6, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 7: dispatch(ols_fft_kernel<7, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 8: dispatch(ols_fft_kernel<8, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 9: dispatch(ols_fft_kernel<9, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 10: dispatch(ols_fft_kernel<10, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 11: dispatch(ols_fft_kernel<11, S, F32OUT>, grid, block, stream, t0, t1, A); break;
+        case 12: dispatch(ols_fft_kernel<12, S, F32OUT>, grid, block, stream, t0, t1, A); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -837,17 +846,17 @@ int ols_fft_wg_per_cu(int log2n_fixed, Storage in, bool f32_out) {
 }
 
 hipError_t launch_ols_fft(const LaunchArgs &A, int log2n_fixed, Storage in, bool f32_out,
-                          hipStream_t stream) {
+                          hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
     if (A.n_items <= 0) return hipSuccess;
     switch (in) {
-        case Storage::C64: return launch_typed<Storage::C64, false>(A, log2n_fixed, stream);
-        case Storage::R32: return launch_typed<Storage::R32, false>(A, log2n_fixed, stream);
+        case Storage::C64: return launch_typed<Storage::C64, false>(A, log2n_fixed, stream, t0, t1);
+        case Storage::R32: return launch_typed<Storage::R32, false>(A, log2n_fixed, stream, t0, t1);
         case Storage::F16:
-            return f32_out ? launch_typed<Storage::F16, true>(A, log2n_fixed, stream)
-                           : launch_typed<Storage::F16, false>(A, log2n_fixed, stream);
+            return f32_out ? launch_typed<Storage::F16, true>(A, log2n_fixed, stream, t0, t1)
+                           : launch_typed<Storage::F16, false>(A, log2n_fixed, stream, t0, t1);
         case Storage::BF16:
-            return f32_out ? launch_typed<Storage::BF16, true>(A, log2n_fixed, stream)
-                           : launch_typed<Storage::BF16, false>(A, log2n_fixed, stream);
+            return f32_out ? launch_typed<Storage::BF16, true>(A, log2n_fixed, stream, t0, t1)
+                           : launch_typed<Storage::BF16, false>(A, log2n_fixed, stream, t0, t1);
     }
     return hipErrorInvalidValue;
 }

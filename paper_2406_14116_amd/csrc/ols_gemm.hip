@@ -26,6 +26,7 @@
 // values below 2^-20 of their block's largest contribute with absolute error
 // (about 2^-31 of that largest).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
@@ -487,8 +488,14 @@ __global__ __launch_bounds__(kThreads) void ols_gemm_kernel(const LaunchArgs A) 
     }
 }
 
-template <Storage S, bool F32OUT> hipError_t launch_g(const LaunchArgs &A, hipStream_t s) {
-    hipLaunchKernelGGL((ols_gemm_kernel<S, F32OUT>), dim3(A.n_wg), dim3(kThreads), 0, s, A);
+// With events, through hipExtLaunchKernel, which records the kernel's own
+// start and end time in them.
+template <Storage S, bool F32OUT>
+hipError_t launch_g(const LaunchArgs &A, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (t0 || t1)
+        hipExtLaunchKernelGGL(ols_gemm_kernel<S, F32OUT>, dim3(A.n_wg), dim3(kThreads), 0, s, t0, t1, 0, A);
+    else
+        hipLaunchKernelGGL((ols_gemm_kernel<S, F32OUT>), dim3(A.n_wg), dim3(kThreads), 0, s, A);
     return hipGetLastError();
 }
 
@@ -506,11 +513,14 @@ int ols_gemm_wg_per_cu(Storage in, bool f32_out) {
     return 1;
 }
 
-hipError_t launch_ols_gemm(const LaunchArgs &A, Storage in, bool f32_out, hipStream_t stream) {
+hipError_t launch_ols_gemm(const LaunchArgs &A, Storage in, bool f32_out, hipStream_t stream, hipEvent_t t0,
+                           hipEvent_t t1) {
     if (A.n_items <= 0 || A.n_wg <= 0) return hipSuccess;
-    if (in == Storage::F16) return f32_out ? launch_g<Storage::F16, true>(A, stream) : launch_g<Storage::F16, false>(A, stream);
+    if (in == Storage::F16)
+        return f32_out ? launch_g<Storage::F16, true>(A, stream, t0, t1) : launch_g<Storage::F16, false>(A, stream, t0, t1);
     if (in == Storage::BF16)
-        return f32_out ? launch_g<Storage::BF16, true>(A, stream) : launch_g<Storage::BF16, false>(A, stream);
+        return f32_out ? launch_g<Storage::BF16, true>(A, stream, t0, t1)
+                       : launch_g<Storage::BF16, false>(A, stream, t0, t1);
     return hipErrorInvalidValue;
 }
 

@@ -725,10 +725,18 @@ vbw::LaunchArgs launch_args(const vbw_plan_s *p) {
     return a;
 }
 
+// Events that take the start of a call's first filter kernel and the end of
+// its last (vbw_filter_timed); null: none.
+struct KernelTimes {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // The filter launches of one variant, with the tables `a` points at
-// (a.wg_begin: the start of the plan's concatenated range tables).
+// (a.wg_begin: the start of the plan's concatenated range tables).  marks:
+// events recorded on the stream before each launch and after the last (the
+// autotuner's); kt: the kernels' own start and end times.
 hipError_t launch_variant(const vbw_plan_s *p, vbw::LaunchArgs a, hipStream_t s, int variant,
-                          hipEvent_t *marks = nullptr) {
+                          hipEvent_t *marks = nullptr, KernelTimes kt = {}) {
     const int32_t *wg0 = a.wg_begin;
     const bool f32 = (p->flags & VBW_F32_OUT) != 0;
     const auto &launches = p->variants[size_t(variant)];
@@ -737,10 +745,17 @@ hipError_t launch_variant(const vbw_plan_s *p, vbw::LaunchArgs a, hipStream_t s,
         a.wg_begin = wg0 + g.wg_off;
         a.n_wg = g.n_wg;
         a.prune = g.prune;
+        const hipEvent_t t0 = i == 0 ? kt.start : nullptr;
+        const hipEvent_t t1 = i + 1 == launches.size() ? kt.stop : nullptr;
         hipError_t e = marks ? hipEventRecord(marks[i], s) : hipSuccess;
         if (e == hipSuccess)
-            e = g.log2n < 0 ? vbw::launch_ols_gemm(a, storage_of(p->dtype), f32, s)
-                            : vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), f32, s);
+            e = g.log2n < 0 ? vbw::launch_ols_gemm(a, storage_of(p->dtype), f32, s, t0, t1)
+                            : vbw::launch_ols_fft(a, g.log2n, storage_of(p->dtype), f32, s, t0, t1);
+        if (e != hipSuccess) return e;
+    }
+    if (launches.empty() && kt.start) {   // nothing to filter: an empty interval
+        hipError_t e = hipEventRecord(kt.start, s);
+        if (e == hipSuccess) e = hipEventRecord(kt.stop, s);
         if (e != hipSuccess) return e;
     }
     return marks ? hipEventRecord(marks[launches.size()], s) : hipSuccess;
@@ -749,9 +764,9 @@ hipError_t launch_variant(const vbw_plan_s *p, vbw::LaunchArgs a, hipStream_t s,
 // The filter launches of one variant; on a streaming plan `advance` then
 // moves every channel's history and block counter past this call (the
 // autotuner's trial runs leave them alone).
-hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant, bool advance = true) {
+hipError_t launch(const vbw_plan_s *p, hipStream_t s, int variant, bool advance = true, KernelTimes kt = {}) {
     const vbw::LaunchArgs a = launch_args(p);
-    hipError_t e = launch_variant(p, a, s, variant);
+    hipError_t e = launch_variant(p, a, s, variant, nullptr, kt);
     if (e != hipSuccess) return e;
     if (advance && (p->flags & VBW_STREAM))
         return vbw::launch_stream_update(a, int(p->ch.size()), storage_of(p->dtype), p->d_hist, p->d_block0, s);
@@ -998,7 +1013,8 @@ vbw_status vbw_plan_set_variant(vbw_plan_t p, int32_t variant) {
 
 void vbw_test_fail_device_alloc(int32_t k) { g_fail_alloc_at = k > 0 ? k : 0; }
 
-static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream);
+static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream,
+                              KernelTimes kt = {});
 
 // Calls on one plan run in call order: a call on another stream than the
 // plan's last call first waits, on the device, for that call's work (it may
@@ -1026,7 +1042,20 @@ vbw_status vbw_filter(vbw_plan_t p, const void *const *x, void *const *y, void *
     }
 }
 
-static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream) {
+vbw_status vbw_filter_timed(vbw_plan_t p, const void *const *x, void *const *y, void *stream, void *start_event,
+                            void *stop_event) {
+    const Range range("vbw_filter_timed");
+    if (!start_event || !stop_event) return VBW_EINVAL;
+    if (p && (p->flags & VBW_GRAPH)) return VBW_EUNSUPPORTED;
+    try {
+        return filter_impl(p, x, y, stream,
+                           {static_cast<hipEvent_t>(start_event), static_cast<hipEvent_t>(stop_event)});
+    } catch (const std::bad_alloc &) {
+        return VBW_ENOMEM;
+    }
+}
+
+static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y, void *stream, KernelTimes kt) {
     if (!p || !x || !y) return VBW_EINVAL;
     if (p->host_only) return VBW_EUNSUPPORTED;
     const size_t nch = p->ch.size();
@@ -1058,8 +1087,12 @@ static vbw_status filter_impl(vbw_plan_t p, const void *const *x, void *const *y
             }
             if (st == VBW_OK) st = from_hip(hipGraphLaunch(p->graph_exec, s));
         } else {
-            st = from_hip(launch(p, s, p->variant));
+            st = from_hip(launch(p, s, p->variant, true, kt));
         }
+    } else if (st == VBW_OK && kt.start) {   // nothing to filter: an empty interval
+        e = hipEventRecord(kt.start, s);
+        if (e == hipSuccess) e = hipEventRecord(kt.stop, s);
+        st = from_hip(e);
     }
     if (st == VBW_OK) st = from_hip(record_done(p, s));
     if (prev != p->device) (void)hipSetDevice(prev);

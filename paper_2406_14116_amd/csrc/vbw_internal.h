@@ -73,12 +73,16 @@ int ols_fft_wg_per_cu(int log2n_fixed, Storage in, bool f32_out);
 
 // Host launchers (ols_fft.hip).  log2n_fixed = 0 selects the kernel that
 // dispatches on each item's N; otherwise every item must have that N.
+// t_start / t_stop (optional): events that take the kernel's own start and
+// end time (hipExtLaunchKernel).
 hipError_t launch_ols_fft(const LaunchArgs &args, int log2n_fixed, Storage in,
-                          bool f32_out, hipStream_t stream);
+                          bool f32_out, hipStream_t stream, hipEvent_t t_start = nullptr,
+                          hipEvent_t t_stop = nullptr);
 
 // Matrix-core engine (ols_gemm.hip): N = 256, 16-bit storage only.
 int ols_gemm_wg_per_cu(Storage in, bool f32_out);
-hipError_t launch_ols_gemm(const LaunchArgs &args, Storage in, bool f32_out, hipStream_t stream);
+hipError_t launch_ols_gemm(const LaunchArgs &args, Storage in, bool f32_out, hipStream_t stream,
+                           hipEvent_t t_start = nullptr, hipEvent_t t_stop = nullptr);
 
 // Streaming continuation (stream.hip): after a call, every channel's history
 // becomes the last N - hop input samples of the call and its block counter

@@ -66,6 +66,8 @@ def lib():
         L.vbw_set_bandwidth.restype = ctypes.c_int
         L.vbw_filter.argtypes = [P, P, P, P]
         L.vbw_filter.restype = ctypes.c_int
+        L.vbw_filter_timed.argtypes = [P, P, P, P, P, P]
+        L.vbw_filter_timed.restype = ctypes.c_int
         L.vbw_destroy.argtypes = [P]
         L.vbw_destroy.restype = None
         L.vbw_strerror.argtypes = [ctypes.c_int]
@@ -272,6 +274,24 @@ class Plan:
         likewise, or (len, 2) float32 / complex64 with F32_OUT.  Runs on ``stream`` (default: torch's current)."""
         self._check_tensors(xs, ys)
         self.filter_ptrs([t.data_ptr() for t in xs], [t.data_ptr() for t in ys], _stream_handle(stream))
+
+    def filter_timed(self, xs, ys, start, stop, stream=None) -> None:
+        """vbw_filter_timed: as ``filter``; ``start`` / ``stop`` (torch.cuda.Event
+        with timing, already created, i.e. recorded once) take the kernels' own
+        start and end time, so ``start.elapsed_time(stop)`` is their duration."""
+        self._check_tensors(xs, ys)
+        for i, t in enumerate(xs):
+            self._xp[i] = t.data_ptr() or None
+        for i, t in enumerate(ys):
+            self._yp[i] = t.data_ptr() or None
+        handles = [int(e.cuda_event) if hasattr(e, "cuda_event") else int(e) for e in (start, stop)]
+        if not all(handles):
+            raise ValueError("events must exist: record each once before passing it")
+        rc = lib().vbw_filter_timed(self.handle, ctypes.cast(self._xp, ctypes.c_void_p),
+                                    ctypes.cast(self._yp, ctypes.c_void_p), _stream_handle(stream) or None,
+                                    handles[0], handles[1])
+        if rc != VBW_OK:
+            raise VbwError(rc, "vbw_filter_timed")
 
     def bind(self, xs, ys):
         """Check the tensors once and return ``run(stream=None)``, which filters

@@ -14,9 +14,13 @@
 
 namespace vbw {
 int ols_fft_wg_per_cu(int, Storage, bool) { return 1; }
-hipError_t launch_ols_fft(const LaunchArgs &, int, Storage, bool, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_ols_fft(const LaunchArgs &, int, Storage, bool, hipStream_t, hipEvent_t, hipEvent_t) {
+    return hipErrorInvalidValue;
+}
 int ols_gemm_wg_per_cu(Storage, bool) { return 1; }
-hipError_t launch_ols_gemm(const LaunchArgs &, Storage, bool, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_ols_gemm(const LaunchArgs &, Storage, bool, hipStream_t, hipEvent_t, hipEvent_t) {
+    return hipErrorInvalidValue;
+}
 hipError_t launch_stream_update(const LaunchArgs &, int, Storage, void *, int64_t *, hipStream_t) {
     return hipErrorInvalidValue;
 }
@@ -81,6 +85,7 @@ int main() {
         CHECK(vbw_set_bandwidth(p, nch, 1, 0) == VBW_EINVAL);
         CHECK(vbw_set_bandwidth(p, 0, 0, 0) == VBW_ERANGE);
         CHECK(vbw_filter(p, nullptr, nullptr, nullptr) == VBW_EINVAL);
+        CHECK(vbw_filter_timed(p, nullptr, nullptr, nullptr, nullptr, nullptr) == VBW_EINVAL);
         vbw_destroy(p);
     }
     // every validation error path

@@ -40,6 +40,8 @@ def test_counters_ignored_for_another_kernel_source(tmp_path, monkeypatch):
     src = os.path.join(bench.PROFILE_DIR, f"ols_fft_{key}_pmc.md")
     shutil.copy(src, tmp_path / os.path.basename(src))
     monkeypatch.setattr(bench, "PROFILE_DIR", str(tmp_path))
+    taken_on = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", open(src).read()).group(1)
+    monkeypatch.setattr(bench, "kernel_hash", lambda engine: taken_on)
     assert bench.counters_from_profile("ols_fft", key, "fft")[0] is not None
     monkeypatch.setattr(bench, "kernel_hash", lambda engine: "0" * 16)
     assert bench.counters_from_profile("ols_fft", key, "fft") == (None, {})

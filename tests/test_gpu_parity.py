@@ -324,6 +324,74 @@ def test_bitwise_identical_across_launch_schedules():
     say("launch variants bitwise identical:", n_var)
 
 
+def test_filter_timed_matches_filter_and_brackets_the_kernels():
+    """vbw_filter_timed computes what vbw_filter computes, bit for bit, on
+    both engines and on a plan whose call is several launches, and its events
+    bracket the kernels: a positive interval no longer than the pair of
+    events recorded on the stream around the same call.  A VBW_GRAPH plan
+    refuses it; a plan with nothing to filter records both events."""
+    rng = np.random.default_rng(12)
+    specs = [(1024, 768, 16, 60, 300000, (1024, 16)), (256, 192, 8, 20, 100000, (256, 8)),
+             (2048, 1536, 8, 300, 50000, (2048, 8))]
+    v_sets = v_for({(1024, 16), (256, 8), (2048, 8)})
+    chans, pool = channels_from(specs, v_sets)
+    xs = [torch.from_numpy(crandn(rng, s[4])).cuda() for s in specs]
+    s = torch.cuda.Stream()
+
+    def events():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for e in ev:
+            e.record(s)                      # created before use
+        s.synchronize()
+        return ev
+
+    p = vbw.Plan(chans, pool)
+    say("launches per call", len(set(specs)), "variant", p.query(vbw.Q_VARIANT))
+    want = [torch.empty_like(x) for x in xs]
+    got = [torch.full_like(x, complex(np.nan, np.nan)) for x in xs]
+    run_plan(p, xs, want, s)
+    a, b, c, d = events()
+    c.record(s)
+    p.filter_timed(xs, got, a, b, s)
+    d.record(s)
+    s.synchronize()
+    kern, pair = a.elapsed_time(b), c.elapsed_time(d)
+    say("kernels", kern, "ms; events around the call", pair, "ms")
+    assert 0 < kern <= pair
+    for y, e in zip(got, want):
+        assert torch.equal(torch.view_as_real(y), torch.view_as_real(e))
+    p.close()
+
+    # matrix-core engine
+    w = wl.config4(storage="f16", n_channels=2, length=1 << 16)
+    x16 = harness.upload_inputs(w, "f16")
+    y0, y1 = harness.alloc_outputs(w, "f16"), harness.alloc_outputs(w, "f16")
+    pg = vbw.Plan.from_workload(w, engine="gemm")
+    run_plan(pg, x16, y0, s)
+    a, b, _, _ = events()
+    pg.filter_timed(x16, y1, a, b, s)
+    s.synchronize()
+    assert a.elapsed_time(b) > 0
+    for u, v in zip(y0, y1):
+        assert torch.equal(u, v)
+    pg.close()
+
+    graph = vbw.Plan(chans, pool, flags=vbw.GRAPH)
+    a, b, _, _ = events()
+    with pytest.raises(vbw.VbwError) as err:
+        graph.filter_timed(xs, got, a, b, s)
+    assert err.value.status == vbw.VBW_EUNSUPPORTED
+    graph.close()
+
+    empty = vbw.Plan([dict(n=256, hop=192, lv=8, v_offset=0, k1=20, len=0)], v_sets[(256, 8)])
+    a, b, _, _ = events()
+    empty.filter_timed([torch.empty(0, dtype=torch.complex64, device="cuda")],
+                       [torch.empty(0, dtype=torch.complex64, device="cuda")], a, b, s)
+    s.synchronize()
+    assert a.elapsed_time(b) >= 0
+    empty.close()
+
+
 def test_graph_replay_matches_eager():
     rng = np.random.default_rng(4)
     specs = [(1024, 768, 16, 60, 200000, (1024, 16)), (2048, 1536, 8, 300, 100000, (2048, 8))]
