@@ -156,6 +156,25 @@ def accuracy(w, dtype, ys, oracle_sample, n_channels: int = 4):
     return dbs
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_2406_14116_amd", "tune_mi355x.txt")
+
+
+def tune_cache_file(arg):
+    """(path, note) of the autotuner choice file for the plan: the given
+    path, none for '', else a temporary copy of the package's MI355X file."""
+    if arg == "":
+        return None, ""
+    if arg is not None:
+        return arg, f" ({arg})"
+    import shutil
+    import tempfile
+    fd, tmp = tempfile.mkstemp(prefix="vbw_tune_", suffix=".txt")
+    os.close(fd)
+    if os.path.exists(TUNE_CACHE):
+        shutil.copyfile(TUNE_CACHE, tmp)
+    return tmp, " (paper_2406_14116_amd/tune_mi355x.txt)"
+
+
 def copy_bandwidth(nbytes: int, steps: int = 10):
     """GB/s of a plain device copy of nbytes (library copy kernel and torch's
     copy), counting read + write bytes like the filter's algorithmic bytes."""
@@ -244,9 +263,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=None,
-                    help="plan flags (default: AUTOTUNE|GRAPH for config 3, the batched steady state; 0 otherwise)")
+                    help="plan flags (default: AUTOTUNE, the launch shape timed on the caller's buffers in the "
+                         "first, untimed call; with GRAPH for config 3, the batched steady state)")
     ap.add_argument("--variant", type=int, default=None,
                     help="fix the plan's launch variant (vbw_plan_set_variant) instead of the default or autotuned one")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner choice file to read and extend (default: a temporary copy of the choices "
+                         "kept for MI355X in the package, so that the run takes them without timing and "
+                         "writes nothing into the tree; '' for none)")
     ap.add_argument("--engine", choices=("fft", "gemm"), default="fft",
                     help="gemm: matrix-core DFTs (16-bit storage, N = 256: config 4)")
     ap.add_argument("--storage", choices=("f16", "bf16"), default="f16", help="config 4 storage")
@@ -269,7 +293,7 @@ def main():
     from paper_2406_14116_amd import harness, vbw
 
     if args.flags is None:
-        args.flags = (vbw.AUTOTUNE | vbw.GRAPH) if args.config == 3 else 0
+        args.flags = vbw.AUTOTUNE | (vbw.GRAPH if args.config == 3 else 0)
     w, dtype = make_workload(args.config, args.storage, args.real)
     log(f"bench: {w.name}: {len(w.channels)} channels, {w.total_samples()} samples, storage {dtype}")
     if args.copy_calibration:
@@ -288,7 +312,9 @@ def main():
     xs = harness.upload_inputs(w, dtype)
     ys = harness.alloc_outputs(w, dtype)
     log(f"bench: inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
-    plan = vbw.Plan.from_workload(w, dtype=dtype, engine=args.engine, flags=args.flags)
+    cache, cache_note = tune_cache_file(args.tune_cache)
+    before = os.path.getsize(cache) if cache and os.path.exists(cache) else 0
+    plan = vbw.Plan.from_workload(w, dtype=dtype, engine=args.engine, flags=args.flags, tune_cache=cache)
     if args.variant is not None:
         plan.set_variant(args.variant)
     # a stream of its own (graph replay needs one other than the null stream)
@@ -298,6 +324,11 @@ def main():
     for _ in range(args.warmup):
         plan.filter(xs, ys, stream)
     torch.cuda.synchronize()
+    if args.flags & vbw.AUTOTUNE and args.variant is None:
+        grew = cache and os.path.exists(cache) and os.path.getsize(cache) > before
+        cache_note = ("timed in this run's first call" if not cache or grew else "kept choice") + cache_note
+    else:
+        cache_note = "fixed" if args.variant is not None else "default shape"
 
     # Launch duration: a pair of events per call that take the filter kernels'
     # own start and end time (vbw_filter_timed); a graph-replayed plan gets a
@@ -365,6 +396,7 @@ def main():
                    "n": c0.n if args.config != 3 else "mixed", "hop": c0.hop if args.config != 3 else "3N/4",
                    "storage": dtype, "engine": args.engine, "flags": args.flags,
                    "variant": plan.query(vbw.Q_VARIANT), "variants_searched": plan.query(vbw.Q_N_VARIANTS),
+                   "variant_from": cache_note,
                    "description": w.description},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, **busy,
@@ -382,6 +414,8 @@ def main():
                                   "oracle on the unquantized input (end to end: input and output rounding)"},
     }
     plan.close()
+    if args.tune_cache is None and cache:
+        os.unlink(cache)
     print(json.dumps(line), flush=True)
 
 
