@@ -1268,6 +1268,48 @@ def test_maximum_sizes():
     assert e <= FP32_DB
 
 
+def test_gemm_engine_long_channel():
+    """The matrix-core engine on one FP16 channel of 1.6e9 samples (6.4 GB in,
+    12.9 GB of float32 out): its per-block buffer resources are sized in
+    32-bit arithmetic, saturating while more than 2 GiB remain, so the blocks
+    around the two points where the input and the output remainder fall
+    below that size are checked against the oracle on the stored input, with
+    both ends and the middle."""
+    n, hop, lv, k1 = 256, 192, 8, 24
+    length = 3 * (1 << 29) + 12345
+    g = torch.Generator(device="cuda")
+    g.manual_seed(9)
+    x = torch.randn(length, 2, device="cuda", generator=g).to(torch.float16)
+    y = torch.empty(length, 2, dtype=torch.float32, device="cuda")
+    v = v_for({(n, lv)})[(n, lv)]
+    p = vbw.Plan([dict(n=n, hop=hop, lv=lv, v_offset=0, k1=k1, len=length)], v, dtype="f16", engine="gemm",
+                 flags=vbw.F32_OUT)
+    run_plan(p, [x], [y])
+    p.close()
+    nb = -(-length // hop)
+    cap = 0x7ffff000
+    in_cross = (length - cap // 4 + (n - hop)) // hop        # input bytes left fall to 2 GiB
+    out_cross = (length - cap // 8) // hop                   # float32 output bytes left fall to 2 GiB
+    marks = [0, in_cross, out_cross, nb // 2, nb - 1]
+    blocks = sorted({b + d for b in marks for d in (-2, -1, 0, 1, 2) if 0 <= b + d < nb})
+    lead = -(-(n - hop) // hop)
+    worst = -np.inf
+    for b in blocks:
+        b0 = min(b, lead)
+        start = (b - b0) * hop
+        hi = min(length, (b + 1) * hop)
+        xloc = harness.storage_to_c128(x[start:hi])
+        ref = ols.blocks_hfso(xloc, n, hop, v, [(0, k1)], blocks=[b0])[0][: hi - b * hop]
+        yb = y[b * hop:hi].cpu().numpy().astype(np.float64)
+        got = yb[:, 0] + 1j * yb[:, 1]
+        e = ols.error_db(got, ref)
+        worst = max(worst, e)
+        assert e <= GEMM_COMPUTE_DB, (b, e)
+    say("1.6e9-sample FP16 channel, matrix-core engine, %d blocks checked: worst dB" % len(blocks), worst)
+    del x, y
+    torch.cuda.empty_cache()
+
+
 def test_readme_usage_example_runs():
     """The usage example of the repository's README, run as written (design the
     transition values, plan, change the band, filter), then checked against the
