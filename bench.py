@@ -157,6 +157,7 @@ def accuracy(w, dtype, ys, oracle_sample, n_channels: int = 4):
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2406_14116_amd", "tune_mi355x.txt")
+WARMUP_SECONDS = 0.15
 
 
 def tune_cache_file(arg):
@@ -222,6 +223,8 @@ def bench_stream(args, w, dtype):
     stream = torch.cuda.current_stream()
     run = plan.bind(xs, ys)          # buffers checked once; each call is the library call only
     s = stream.cuda_stream
+    if args.warmup is None:
+        args.warmup = 3
     for _ in range(args.warmup * C):
         run(s)
     torch.cuda.synchronize()
@@ -258,7 +261,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed calls before the K timed ones (default: as many as fill about 0.15 s, at "
+                         "least 3: the clocks reach their sustained state only after some tens of ms of load)")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -300,6 +305,7 @@ def main():
         nbytes = w.total_samples() * (8 if dtype == "c64" else 4)
         x = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda").normal_()
         y = torch.empty_like(x)
+        args.warmup = 3 if args.warmup is None else args.warmup
         for _ in range(args.warmup + args.steps):
             vbw.copy(x, y)
         torch.cuda.synchronize()
@@ -321,7 +327,18 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
+    # untimed calls; the first one autotunes when the plan has no kept choice
+    done = 0
+    if args.warmup is None:
+        t_call = float("inf")
+        for _ in range(3):           # one call's time, after the first call's set-up
+            t0 = time.perf_counter()
+            plan.filter(xs, ys, stream)
+            torch.cuda.synchronize()
+            t_call = min(t_call, time.perf_counter() - t0)
+        done = 3
+        args.warmup = max(3, int(np.ceil(WARMUP_SECONDS / max(t_call, 1e-6))))
+    for _ in range(args.warmup - done):
         plan.filter(xs, ys, stream)
     torch.cuda.synchronize()
     if args.flags & vbw.AUTOTUNE and args.variant is None:
