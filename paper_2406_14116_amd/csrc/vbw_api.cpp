@@ -870,33 +870,43 @@ vbw_status autotune(vbw_plan_s *p, hipStream_t s) {
     for (auto &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
     const vbw::LaunchArgs args = launch_args(p);
+    const size_t n_var = p->variants.size();
+    // Rounds that visit every variant in turn, each variant keeping its
+    // fastest round: a clock that is still rising (or falling) under the
+    // first sustained load moves all variants alike instead of favouring the
+    // ones timed last.
+    constexpr int kRounds = 4;
+    constexpr float kInf = 3.0e38f;
+    std::vector<float> total(n_var, kInf);
+    std::vector<std::vector<float>> group(n_var, std::vector<float>(n_groups, kInf));
+    for (size_t v = 0; e == hipSuccess && v < n_var; ++v) e = launch_variant(p, args, s, int(v));   // warm-up
+    for (int r = 0; r < kRounds && e == hipSuccess; ++r) {
+        for (size_t v = 0; e == hipSuccess && v < n_var; ++v) {
+            e = launch_variant(p, args, s, int(v), ev.data());
+            if (e == hipSuccess) e = hipEventSynchronize(ev[p->variants[v].size()]);
+            float sum = 0.f;
+            for (size_t g = 0; e == hipSuccess && g < p->variants[v].size(); ++g) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, ev[g], ev[g + 1]);
+                group[v][g] = std::min(group[v][g], ms);
+                sum += ms;
+            }
+            total[v] = std::min(total[v], sum);
+        }
+    }
     float best = 0.f;
     int best_v = 0;
     std::vector<float> group_best(n_groups, 0.f);
     std::vector<int> group_choice(n_groups, 0);
-    constexpr int kReps = 3;
-    for (size_t v = 0; e == hipSuccess && v < p->variants.size(); ++v) {
-        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_variant(p, args, s, int(v));
-        std::vector<float> per(n_groups + 1, 0.f);
-        for (int r = 0; r < kReps && e == hipSuccess; ++r) {
-            e = launch_variant(p, args, s, int(v), ev.data());
-            if (e == hipSuccess) e = hipEventSynchronize(ev[p->variants[v].size()]);
-            for (size_t g = 0; e == hipSuccess && g < p->variants[v].size(); ++g) {
-                float ms = 0.f;
-                e = hipEventElapsedTime(&ms, ev[g], ev[g + 1]);
-                per[g] += ms;
-                per[n_groups] += ms;
-            }
-        }
-        if (e != hipSuccess) break;
-        if (v == 0 || per[n_groups] < best) {
-            best = per[n_groups];
+    for (size_t v = 0; e == hipSuccess && v < n_var; ++v) {
+        if (v == 0 || total[v] < best) {
+            best = total[v];
             best_v = int(v);
         }
         if (v < p->shapes.size() && !p->shapes[v].dispatch)
             for (size_t g = 0; g < n_groups; ++g)
-                if (v == 0 || per[g] < group_best[g]) {
-                    group_best[g] = per[g];
+                if (v == 0 || group[v][g] < group_best[g]) {
+                    group_best[g] = group[v][g];
                     group_choice[g] = int(v);
                 }
     }
