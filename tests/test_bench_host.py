@@ -49,3 +49,25 @@ def test_counters_ignored_for_another_kernel_source(tmp_path, monkeypatch):
 
 def test_no_profile_no_counters():
     assert bench.counters_from_profile("ols_fft", "no_such_workload", "fft") == (None, {})
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def test_tune_cache_file_is_a_temporary_copy(tmp_path):
+    path, note = bench.tune_cache_file(None)
+    try:
+        assert path != bench.TUNE_CACHE and os.path.exists(path)
+        assert open(path).read() == open(bench.TUNE_CACHE).read()
+        assert "tune_mi355x.txt" in note
+    finally:
+        os.unlink(path)
+    assert bench.tune_cache_file("") == (None, "")
+    given = str(tmp_path / "t.txt")
+    assert bench.tune_cache_file(given)[0] == given
