@@ -108,6 +108,55 @@ def test_noalloc_16bit_matrix_core_engine():
     del rng
 
 
+@pytest.mark.parametrize("dtype,flags", [("r32", 0), ("c64", vbw.NO_PRUNE), ("bf16", vbw.F32_OUT)])
+def test_noalloc_other_storage_and_flags(dtype, flags):
+    """Real input, the unpruned inverse and 16-bit input with float32 output:
+    the same bits as the plan path, and the oracle's result on the stored
+    input."""
+    specs = [(1024, 768, 16, 100, 200_003), (256, 192, 8, 30, 50_000), (2048, 1536, 16, 400, 30_001)]
+    chans, pool, vs, xs, sw = make_case(31, specs)
+    if dtype == "r32":
+        xt = [torch.from_numpy(np.ascontiguousarray(x.real)).cuda() for x in xs]
+        stored = [x.real.astype(np.complex128) for x in xs]
+    elif dtype == "bf16":
+        xt = [torch.from_numpy(np.stack([x.real, x.imag], 1)).to(torch.bfloat16).cuda() for x in xs]
+        stored = [t.float().cpu().numpy() @ np.array([1.0, 1.0j]) for t in xt]
+    else:
+        xt = [torch.from_numpy(x).cuda() for x in xs]
+        stored = [x.astype(np.complex128) for x in xs]
+    outs = []
+    for use_plan in (True, False):
+        if dtype == "bf16":
+            ys = [torch.full((t.shape[0], 2), float("nan"), device="cuda") for t in xt]
+        else:
+            ys = [torch.full_like(t, float("nan")) for t in xt]
+        if use_plan:
+            plan = vbw.Plan(chans, pool, dtype=dtype, flags=flags)
+            for c, k1, b in sw:
+                plan.set_bandwidth(c, k1, b)
+            plan.filter(xt, ys)
+            torch.cuda.synchronize()
+            plan.close()
+        else:
+            vbw.filter_noalloc(chans, pool, xt, ys, dtype=dtype, flags=flags, switches=sw)
+        torch.cuda.synchronize()
+        outs.append([y.cpu().numpy() for y in ys])
+    for a, b in zip(*outs):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    for i, (c, x, y) in enumerate(zip(chans, stored, outs[1])):
+        sched = [(0, c["k1"])] + sorted((bb, k) for (ch, k, bb) in sw if ch == i)
+        ref = ols.channel_hfso(x, c["n"], c["hop"], vs[i], sched)
+        if dtype == "r32":          # a real filter on real input: the oracle's real part
+            got, ref = y.astype(np.float64), ref.real
+        elif dtype == "bf16":       # float32 output pairs
+            got = y.astype(np.float64) @ np.array([1.0, 1.0j])
+        else:
+            got = y.astype(np.complex128)
+        err = ols.error_db(got, ref)
+        say(f"  {dtype} channel {i}: {err:.1f} dB vs oracle")
+        assert err <= FP32_DB, (i, err)
+
+
 def test_noalloc_rejects_what_it_cannot_serve():
     chans = [dict(n=256, hop=192, lv=4, v_offset=0, k1=10, len=1000)]
     pool = np.array([0.9, 0.7, 0.4, 0.1])
