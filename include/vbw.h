@@ -30,9 +30,14 @@
  *               The impulse response is real (eq. (8)), so the library
  *               filters two consecutive real blocks as the real and imaginary
  *               parts of one complex block.
- * Arithmetic is float32 in every case; 16-bit values are converted on load
- * and rounded to nearest-even on store.  With VBW_F32_OUT the output is
- * written as float32 pairs whatever the input storage.
+ * The FFT engine computes in float32.  The matrix-core engine
+ * (VBW_ENGINE_GEMM) feeds its products FP16 hi/lo operand pairs and
+ * accumulates in float32, after an exact power-of-two scale per block; its
+ * error relative to each block's largest value is about the float32
+ * engine's, for any finite FP16 or BF16 input (FP16 subnormals to 65504,
+ * BF16 over its whole range).  16-bit values are converted on load and
+ * rounded to nearest-even on store.  With VBW_F32_OUT the output is written
+ * as float32 pairs whatever the input storage.
  *
  * Errors: every entry point returns a vbw_status; negative values are errors.
  * No exception crosses the ABI and nothing aborts.  A call that fails leaves
@@ -75,7 +80,8 @@ typedef enum vbw_dtype {
 typedef enum vbw_engine {
     VBW_ENGINE_FFT = 0,     /* LDS-staged Stockham FFT, float32 */
     VBW_ENGINE_GEMM = 1     /* N = 256 as 16 x 16 MFMA products, FP16 hi/lo split
-                               operands, FP32 accumulation (16-bit storage only) */
+                               operands, FP32 accumulation, exact per-block
+                               power-of-two scaling (16-bit storage only) */
 } vbw_engine;
 
 /* Plan flags. */
