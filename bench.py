@@ -366,15 +366,16 @@ def main():
         cache_note = "fixed" if args.variant is not None else "default shape"
 
     # Launch duration: every other call takes a pair of events that record the
-    # filter kernels' own start and end time (vbw_filter_timed); a
-    # graph-replayed plan gets the pair recorded on the stream around the call
-    # instead, which adds the launch latency.  (Events on every call would
-    # lengthen the wall time of the timed region by about 3%: the runtime's
-    # handling of each event sits between consecutive launches.)  The span
-    # from the first timed call's start to the last one's end, per call,
-    # adds the dispatch gaps and is reported beside it.
+    # filter kernels' own start and end time (vbw_filter_timed).  (Events on
+    # every call would lengthen the wall time of the timed region by about 3%:
+    # the runtime's handling of each event sits between consecutive launches.)
+    # The span from the first timed call's start to the last one's end, per
+    # call, adds the dispatch gaps and is reported beside it.  A graph-replayed
+    # plan cannot take kernel events; events recorded around each graph launch
+    # would time the event handling as well, so it gets one pair around the K
+    # calls, and its launch duration is that span per call.
     kernel_events = not (args.flags & vbw.GRAPH)
-    timed = set(range(0, args.steps, 2))
+    timed = set(range(0, args.steps, 2)) if kernel_events else {0, args.steps - 1}
     ev = {i: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for i in timed}
     if kernel_events:
         for a, b in ev.values():   # create the events before they are handed to the library
@@ -388,16 +389,21 @@ def main():
         elif kernel_events:
             plan.filter_timed(xs, ys, ev[i][0], ev[i][1], stream)
         else:
-            ev[i][0].record(stream)
+            if i == 0:
+                ev[i][0].record(stream)
             plan.filter(xs, ys, stream)
-            ev[i][1].record(stream)
+            if i == args.steps - 1:
+                ev[i][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    pairs = [a.elapsed_time(b) for a, b in ev.values()]
-    kernel_ms = float(np.mean(pairs))
     first, last = min(ev), max(ev)
     span_ms = ev[first][0].elapsed_time(ev[last][1]) / (last - first + 1)
+    if kernel_events:
+        pairs = [a.elapsed_time(b) for a, b in ev.values()]
+    else:
+        pairs = [span_ms]
+    kernel_ms = float(np.mean(pairs))
     log(f"bench: {ms_per_step:.3f} ms/step wall, {kernel_ms:.3f} ms/launch (events), "
         f"{span_ms:.3f} ms/launch over the span")
 
@@ -438,9 +444,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, **busy,
                      "kernel_ms": kernel_ms, "kernel_ms_median": float(np.median(pairs)),
-                     "span_ms_per_launch": span_ms, "timed_calls": len(pairs),
+                     "span_ms_per_launch": span_ms, "timed_calls": len(pairs) if kernel_events else args.steps,
                      "launch_timing": "kernel start/end events (vbw_filter_timed)" if kernel_events
-                                      else "events on the stream around each graph launch",
+                                      else "events on the stream around the timed graph launches, per launch",
                      "algorithmic_bytes": total * bytes_per_sample,
                      "copy_gbs": copy, "frac_of_copy": achieved / max(copy.values()),
                      "copy_load_s_before_warmup": args.load_seconds},
