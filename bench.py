@@ -157,8 +157,7 @@ def accuracy(w, dtype, ys, oracle_sample, n_channels: int = 4):
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2406_14116_amd", "tune_mi355x.txt")
-WARMUP_SECONDS = 0.15   # default warm-up: about this long of filter calls
-LOAD_SECONDS = 0.5      # copies before the copy calibration and the warm-up
+WARMUP_SECONDS = 0.15
 
 
 def tune_cache_file(arg):
@@ -177,21 +176,14 @@ def tune_cache_file(arg):
     return tmp, " (paper_2406_14116_amd/tune_mi355x.txt)"
 
 
-def copy_bandwidth(nbytes: int, steps: int = 10, load_s: float = 0.0):
+def copy_bandwidth(nbytes: int, steps: int = 10):
     """GB/s of a plain device copy of nbytes (library copy kernel and torch's
-    copy), counting read + write bytes like the filter's algorithmic bytes.
-    With load_s, the library copy first runs back to back for that long, so
-    that the GPU leaves its idle clock state before anything is timed."""
+    copy), counting read + write bytes like the filter's algorithmic bytes."""
     import torch
     from paper_2406_14116_amd import vbw
     n = nbytes // 8
     x = torch.empty(n, dtype=torch.complex64, device="cuda").normal_()
     y = torch.empty_like(x)
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < load_s:
-        for _ in range(8):
-            vbw.copy(x, y)
-        torch.cuda.synchronize()
     out = {}
     for name, fn in (("vbw_copy", lambda: vbw.copy(x, y)), ("torch_copy", lambda: y.copy_(x))):
         for _ in range(3):
@@ -272,9 +264,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed calls before the K timed ones (default: as many as fill about 0.15 s, at "
                          "least 3: the clocks reach their sustained state only after some tens of ms of load)")
-    ap.add_argument("--load-seconds", type=float, default=LOAD_SECONDS,
-                    help="seconds of back-to-back copies of the workload's bytes before the copy calibration "
-                         "and the warm-up calls")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -329,13 +318,6 @@ def main():
     xs = harness.upload_inputs(w, dtype)
     ys = harness.alloc_outputs(w, dtype)
     log(f"bench: inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
-    total = w.total_samples()
-    bytes_per_sample = 16 if dtype == "c64" else 8
-    # The copy calibration runs first, after --load-seconds of copies:
-    # kernel times fall by 5-8% over the first tens of milliseconds of
-    # sustained load, and both measurements are meant for the loaded state.
-    copy = copy_bandwidth(total * bytes_per_sample // 2, load_s=args.load_seconds)
-    log(f"bench: plain copy of the same bytes: {copy}")
     cache, cache_note = tune_cache_file(args.tune_cache)
     before = os.path.getsize(cache) if cache and os.path.exists(cache) else 0
     plan = vbw.Plan.from_workload(w, dtype=dtype, engine=args.engine, flags=args.flags, tune_cache=cache)
@@ -407,11 +389,15 @@ def main():
     log(f"bench: {ms_per_step:.3f} ms/step wall, {kernel_ms:.3f} ms/launch (events), "
         f"{span_ms:.3f} ms/launch over the span")
 
+    total = w.total_samples()
+    bytes_per_sample = 16 if dtype == "c64" else 8
     achieved = total * bytes_per_sample / (kernel_ms * 1e-3) / 1e9
     key = workload_key(args.config, dtype, args.engine, args.real, args.flags)
     kernel = "ols_gemm" if args.engine == "gemm" else "ols_fft"
     traffic, busy = counters_from_profile(kernel, key, args.engine)
 
+    copy = copy_bandwidth(total * bytes_per_sample // 2)
+    log(f"bench: plain copy of the same bytes: {copy}")
 
     cpu = None
     sample = None
@@ -448,8 +434,7 @@ def main():
                      "launch_timing": "kernel start/end events (vbw_filter_timed)" if kernel_events
                                       else "events on the stream around the timed graph launches, per launch",
                      "algorithmic_bytes": total * bytes_per_sample,
-                     "copy_gbs": copy, "frac_of_copy": achieved / max(copy.values()),
-                     "copy_load_s_before_warmup": args.load_seconds},
+                     "copy_gbs": copy, "frac_of_copy": achieved / max(copy.values())},
         "cpu_baseline": cpu,
         "accuracy_db": {"max": max(dbs) if dbs else None,
                         "median": float(np.median(dbs)) if dbs else None,
