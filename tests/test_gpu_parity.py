@@ -329,7 +329,8 @@ def test_filter_timed_matches_filter_and_brackets_the_kernels():
     both engines and on a plan whose call is several launches, and its events
     bracket the kernels: a positive interval no longer than the pair of
     events recorded on the stream around the same call.  A VBW_GRAPH plan
-    refuses it; a plan with nothing to filter records both events."""
+    refuses it; a plan with nothing to filter records both events; on a
+    streaming plan it moves the stream on like vbw_filter."""
     rng = np.random.default_rng(12)
     specs = [(1024, 768, 16, 60, 300000, (1024, 16)), (256, 192, 8, 20, 100000, (256, 8)),
              (2048, 1536, 8, 300, 50000, (2048, 8))]
@@ -390,6 +391,39 @@ def test_filter_timed_matches_filter_and_brackets_the_kernels():
     s.synchronize()
     assert a.elapsed_time(b) >= 0
     empty.close()
+
+    # a streaming plan: each timed call still moves the stream on (the state
+    # update runs after the interval), so calls that alternate between
+    # vbw_filter_timed and vbw_filter continue one stream bit for bit like
+    # vbw_filter alone
+    specs = [(256, 192, 8, 24, 9), (1024, 768, 16, 100, 7), (2048, 1536, 16, 300, 3)]
+    calls = 4
+    v_sets = v_for({(n, lv) for (n, _, lv, _, _) in specs})
+    chunk = [blocks * hop for (_, hop, _, _, blocks) in specs]
+    chans, pool = channels_from([(n, hop, lv, k1, c, (n, lv)) for (n, hop, lv, k1, _), c in zip(specs, chunk)],
+                                v_sets)
+    xs = [torch.from_numpy(crandn(rng, c * calls)).cuda() for c in chunk]
+    outs = []
+    for timed in (False, True):
+        ps = vbw.Plan(chans, pool, flags=vbw.STREAM)
+        ys = [torch.full_like(x, complex(np.nan, np.nan)) for x in xs]
+        s.wait_stream(torch.cuda.current_stream())
+        for i in range(calls):
+            xi = [x[i * c:(i + 1) * c] for x, c in zip(xs, chunk)]
+            yi = [y[i * c:(i + 1) * c] for y, c in zip(ys, chunk)]
+            if timed and i % 2 == 0:
+                a, b, _, _ = events()
+                ps.filter_timed(xi, yi, a, b, s)
+                s.synchronize()
+                assert a.elapsed_time(b) > 0
+            else:
+                ps.filter(xi, yi, s)
+        s.synchronize()
+        outs.append(ys)
+        ps.close()
+    for y0, y1 in zip(*outs):
+        assert not torch.isnan(torch.view_as_real(y1)).any()
+        assert torch.equal(torch.view_as_real(y0), torch.view_as_real(y1))
 
 
 def test_graph_replay_matches_eager():
