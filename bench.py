@@ -325,6 +325,10 @@ def main():
         plan.set_variant(args.variant)
     # a stream of its own (graph replay needs one other than the null stream)
     stream = torch.cuda.Stream()
+    # the buffers stay fixed from call to call, so they are checked once and
+    # each call below is the library call alone (Plan.filter checks every
+    # tensor per call: about 37 us of Python for config 2, 270 us for config 3)
+    run = plan.bind(xs, ys)
     torch.cuda.synchronize()
 
     # untimed calls; the first one autotunes when the plan has no kept choice
@@ -333,13 +337,13 @@ def main():
         t_call = float("inf")
         for _ in range(3):           # one call's time, after the first call's set-up
             t0 = time.perf_counter()
-            plan.filter(xs, ys, stream)
+            run(stream)
             torch.cuda.synchronize()
             t_call = min(t_call, time.perf_counter() - t0)
         done = 3
         args.warmup = max(3, int(np.ceil(WARMUP_SECONDS / max(t_call, 1e-6))))
     for _ in range(args.warmup - done):
-        plan.filter(xs, ys, stream)
+        run(stream)
     torch.cuda.synchronize()
     if args.flags & vbw.AUTOTUNE and args.variant is None:
         grew = cache and os.path.exists(cache) and os.path.getsize(cache) > before
@@ -367,13 +371,13 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         if i not in ev:
-            plan.filter(xs, ys, stream)
+            run(stream)
         elif kernel_events:
-            plan.filter_timed(xs, ys, ev[i][0], ev[i][1], stream)
+            run(stream, ev[i][0], ev[i][1])
         else:
             if i == 0:
                 ev[i][0].record(stream)
-            plan.filter(xs, ys, stream)
+            run(stream)
             if i == args.steps - 1:
                 ev[i][1].record(stream)
     torch.cuda.synchronize()

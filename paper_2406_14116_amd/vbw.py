@@ -192,6 +192,16 @@ def _check_tensors(lengths, dtype, flags, xs, ys) -> None:
             raise ValueError("tensors must be contiguous and on the GPU")
 
 
+def _event_handles(start, stop):
+    """HIP event handles of two torch.cuda.Event (or raw handles)."""
+    if start is None or stop is None:
+        raise ValueError("both events are needed")
+    handles = [int(e.cuda_event) if hasattr(e, "cuda_event") else int(e) for e in (start, stop)]
+    if not all(handles):
+        raise ValueError("events must exist: record each once before passing it")
+    return handles[0], handles[1]
+
+
 def _stream_handle(stream) -> int:
     """hipStream_t of a torch stream, an integer handle, or (None) torch's
     current stream."""
@@ -284,31 +294,34 @@ class Plan:
             self._xp[i] = t.data_ptr() or None
         for i, t in enumerate(ys):
             self._yp[i] = t.data_ptr() or None
-        handles = [int(e.cuda_event) if hasattr(e, "cuda_event") else int(e) for e in (start, stop)]
-        if not all(handles):
-            raise ValueError("events must exist: record each once before passing it")
+        a, b = _event_handles(start, stop)
         rc = lib().vbw_filter_timed(self.handle, ctypes.cast(self._xp, ctypes.c_void_p),
-                                    ctypes.cast(self._yp, ctypes.c_void_p), _stream_handle(stream) or None,
-                                    handles[0], handles[1])
+                                    ctypes.cast(self._yp, ctypes.c_void_p), _stream_handle(stream) or None, a, b)
         if rc != VBW_OK:
             raise VbwError(rc, "vbw_filter_timed")
 
     def bind(self, xs, ys):
-        """Check the tensors once and return ``run(stream=None)``, which filters
-        them again on every call with nothing but the library call: the form
-        for ring-buffered streaming (same buffers, new contents each call).
-        ``run`` keeps the tensors alive."""
+        """Check the tensors once and return ``run(stream=None, start=None,
+        stop=None)``, which filters them again on every call with nothing but
+        the library call: the form for fixed buffers whose contents change
+        (ring-buffered streaming, a serving loop).  With ``start`` and ``stop``
+        (events as for ``filter_timed``) the call is vbw_filter_timed.  ``run``
+        keeps the tensors alive."""
         self._check_tensors(xs, ys)
         n = max(1, self.n_channels)
         xp = (ctypes.c_void_p * n)(*[t.data_ptr() or None for t in xs])
         yp = (ctypes.c_void_p * n)(*[t.data_ptr() or None for t in ys])
         xpp, ypp = ctypes.cast(xp, ctypes.c_void_p), ctypes.cast(yp, ctypes.c_void_p)
-        call = lib().vbw_filter
+        call, call_timed = lib().vbw_filter, lib().vbw_filter_timed
 
-        def run(stream=None):
-            rc = call(self.handle, xpp, ypp, _stream_handle(stream) or None)   # raises once the plan is closed
+        def run(stream=None, start=None, stop=None):
+            if start is None and stop is None:
+                rc = call(self.handle, xpp, ypp, _stream_handle(stream) or None)   # raises once the plan is closed
+            else:
+                a, b = _event_handles(start, stop)
+                rc = call_timed(self.handle, xpp, ypp, _stream_handle(stream) or None, a, b)
             if rc != VBW_OK:
-                raise VbwError(rc, "vbw_filter")
+                raise VbwError(rc, "vbw_filter" if start is None and stop is None else "vbw_filter_timed")
         run.tensors = (list(xs), list(ys), xp, yp)
         return run
 

@@ -258,6 +258,24 @@ def test_binding_checks_tensor_types_and_sizes():
     p.close()
 
 
+def test_binding_event_handles():
+    """The timed calls (Plan.filter_timed, a bound run with events) take both
+    events, and only events that exist: a torch event that was never recorded
+    has no HIP event yet, and a null handle would reach the library."""
+    with pytest.raises(ValueError, match="both"):
+        vbw._event_handles(None, 0x10)
+    with pytest.raises(ValueError, match="must exist"):
+        vbw._event_handles(0x10, 0)
+    assert vbw._event_handles(0x10, 0x20) == (0x10, 0x20)
+
+    class Ev:
+        def __init__(self, h):
+            self.cuda_event = h
+    assert vbw._event_handles(Ev(0x30), Ev(0x40)) == (0x30, 0x40)
+    with pytest.raises(ValueError, match="must exist"):
+        vbw._event_handles(Ev(0), Ev(0x40))
+
+
 def test_binding_fails_loudly_without_the_library(tmp_path):
     """With the HIP library absent the binding raises (there is no CPU
     fallback): a fresh interpreter pointed at a missing library path."""

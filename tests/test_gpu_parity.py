@@ -361,6 +361,23 @@ def test_filter_timed_matches_filter_and_brackets_the_kernels():
     assert 0 < kern <= pair
     for y, e in zip(got, want):
         assert torch.equal(torch.view_as_real(y), torch.view_as_real(e))
+    # the bound form, plain and timed
+    got2 = [torch.full_like(x, complex(np.nan, np.nan)) for x in xs]
+    run = p.bind(xs, got2)
+    a, b, _, _ = events()
+    s.wait_stream(torch.cuda.current_stream())       # the NaN fill is done
+    run(s, a, b)
+    s.synchronize()
+    assert a.elapsed_time(b) > 0
+    for y, e in zip(got2, want):
+        assert torch.equal(torch.view_as_real(y), torch.view_as_real(e))
+    for y in got2:
+        y.fill_(complex(np.nan, np.nan))
+    s.wait_stream(torch.cuda.current_stream())
+    run(s)
+    s.synchronize()
+    for y, e in zip(got2, want):
+        assert torch.equal(torch.view_as_real(y), torch.view_as_real(e))
     p.close()
 
     # matrix-core engine
