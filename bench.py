@@ -7,7 +7,13 @@ inputs already resident in HBM.  Default workload: 64 channels x 2^20
 complex64 samples, N = 1024, hop 768, 16 transition values per edge, every
 channel switching bandwidth at block 512.
 
-Prints one JSON line.  `value` is complex output samples per second.  The
+Prints one JSON line.  `value` is complex output samples per second of wall
+time over the K timed calls; `roofline` takes the kernels' launch duration
+from HIP events (the kernels' start and end on every other call; around the
+K calls for a graph-replayed plan).  The timed calls are the library call
+alone: the fixed buffers are checked once (Plan.bind).  Without --warmup,
+about 0.15 s of untimed calls come first, so that the timed calls run past
+the power-management transient of the first tens of milliseconds.  The
 accuracy of the timed output is checked on sampled blocks against the FP64
 oracle (reported in dB); the oracle is also timed on the host cores on a
 bounded sample (`cpu_baseline`).
