@@ -5,6 +5,7 @@ every checked sample; integer work (framing, bin classes, schedule, tails) is
 exercised by cases where any index slip gives an O(1) error.
 """
 import os
+import shutil
 
 import numpy as np
 import pytest
@@ -23,6 +24,33 @@ GEMM_COMPUTE_DB = -120.0
 
 def say(*a):
     print(*a, flush=True)
+
+
+TUNE_FILE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2406_14116_amd",
+                         "tune_mi355x.txt")
+
+
+def timed_shape_plan(w, tmp_path, graph=False, flags=0, **kw):
+    """The plan the benchmark times for workload w: AUTOTUNE (and GRAPH for
+    the batched workload) with the kept launch-shape choices of the package's
+    MI355X file, read from a temporary copy so that nothing is appended to it
+    (a shape the file does not hold is timed on the plan's first call, as in
+    the benchmark)."""
+    cache = tmp_path / "tune.txt"
+    if not cache.exists():
+        shutil.copyfile(TUNE_FILE, cache)
+    return vbw.Plan.from_workload(w, flags=flags | vbw.AUTOTUNE | (vbw.GRAPH if graph else 0),
+                                  tune_cache=str(cache), **kw)
+
+
+def run_timed_shape(plan, xs, ys, tag):
+    """One call on a side stream (graph replay needs a stream other than the
+    null stream), after the uploads on torch's current stream."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    plan.filter(xs, ys, s)
+    s.synchronize()
+    say(tag, ": launch variant", plan.query(vbw.Q_VARIANT), "of", plan.query(vbw.Q_N_VARIANTS))
 
 
 def run_plan(plan, xs, ys, stream=None):
@@ -616,13 +644,15 @@ def check_whole_channel(w, ys, ci, x, tol=FP32_DB, elem=ELEM_FP32):
     return e
 
 
-def test_config2_full_size_sampled():
+def test_config2_full_size_sampled(tmp_path):
+    """Config 2 at its full size in the launch configuration the benchmark
+    times (kept autotuner choice)."""
     w = wl.config2()
     say("config2: uploading", len(w.channels), "channels")
     xs = harness.upload_inputs(w, "c64")
     ys = harness.alloc_outputs(w, "c64")
-    plan = vbw.Plan.from_workload(w)
-    run_plan(plan, xs, ys)
+    plan = timed_shape_plan(w, tmp_path)
+    run_timed_shape(plan, xs, ys, "config2")
     say("config2: filtered; checking")
     dbs = check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128),
                         channels=[0, 1, 31, 63], n_random=6)
@@ -635,7 +665,7 @@ def test_config2_full_size_sampled():
 
 
 @pytest.mark.parametrize("storage,bound", [("f16", -65.0), ("bf16", -50.0)])
-def test_config4_full_size_sampled(storage, bound):
+def test_config4_full_size_sampled(storage, bound, tmp_path):
     """Config 4 at its full size (256 channels x 2^20 16-bit pairs) in the
     launch configuration the benchmark times, both engines: end to end
     against the oracle on the unquantized input, and compute only (float32
@@ -646,16 +676,16 @@ def test_config4_full_size_sampled(storage, bound):
     chans = [0, 1, 127, 255] + list(range(2, 255, 23))
     for engine in ("fft", "gemm"):
         ys = harness.alloc_outputs(w, storage)
-        plan = vbw.Plan.from_workload(w, engine=engine)
-        run_plan(plan, xs, ys)
+        plan = timed_shape_plan(w, tmp_path, engine=engine)
+        run_timed_shape(plan, xs, ys, f"config4 {storage} {engine}")
         plan.close()
         dbs = check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci), tol=bound, channels=chans, n_random=8,
                             elem=ELEM_E2E[storage], block_tol=bound + 6)
         say("config4", storage, engine, "end-to-end dB max/median", max(dbs), float(np.median(dbs)))
         del ys
         ys32 = harness.alloc_outputs(w, storage, f32_out=True)
-        p32 = vbw.Plan.from_workload(w, engine=engine, flags=vbw.F32_OUT)
-        run_plan(p32, xs, ys32)
+        p32 = timed_shape_plan(w, tmp_path, engine=engine, flags=vbw.F32_OUT)
+        run_timed_shape(p32, xs, ys32, f"config4 {storage} {engine} float32 output")
         p32.close()
         dbs = check_sampled(w, ys32, lambda ci: harness.storage_to_c128(xs[ci]), channels=chans, n_random=8,
                             tol=FP32_DB if engine == "fft" else GEMM_COMPUTE_DB,
@@ -671,13 +701,15 @@ def test_config4_full_size_sampled(storage, bound):
     torch.cuda.empty_cache()
 
 
-def test_config3_full_size_sampled():
+def test_config3_full_size_sampled(tmp_path):
+    """Config 3 at its full size in the launch configuration the benchmark
+    times: kept autotuner choice, replayed from a HIP graph."""
     w = wl.config3()
     say("config3: uploading", len(w.channels), "channels")
     xs = harness.upload_inputs(w, "c64")
     ys = harness.alloc_outputs(w, "c64")
-    plan = vbw.Plan.from_workload(w)
-    run_plan(plan, xs, ys)
+    plan = timed_shape_plan(w, tmp_path, graph=True)
+    run_timed_shape(plan, xs, ys, "config3")
     say("config3: filtered; checking")
     chans = list(range(0, 512, 16)) + [511]
     dbs = check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128),
@@ -690,13 +722,15 @@ def test_config3_full_size_sampled():
     plan.close()
 
 
-def test_config5_full_size_sampled():
+def test_config5_full_size_sampled(tmp_path):
+    """Config 5 at its full size in the launch configuration the benchmark
+    times (kept autotuner choice)."""
     w = wl.config5()
     say("config5: uploading", len(w.channels), "channels x", w.channels[0].length)
     xs = harness.upload_inputs(w, "c64")
     ys = harness.alloc_outputs(w, "c64")
-    plan = vbw.Plan.from_workload(w)
-    run_plan(plan, xs, ys)
+    plan = timed_shape_plan(w, tmp_path)
+    run_timed_shape(plan, xs, ys, "config5")
     say("config5: filtered; checking")
     dbs = check_sampled(w, ys, lambda ci: wl.channel_samples(w, ci, dtype=np.complex64).astype(np.complex128),
                         channels=[0, 100, 255], n_random=8)
@@ -1120,14 +1154,15 @@ def test_real_input_long_spans_and_band_switches(cap):
             assert ols.error_db(y[sl], ref[sl]) <= FP32_DB + 10, (spec, m)
 
 
-def test_real_input_config2_full_size_sampled():
+def test_real_input_config2_full_size_sampled(tmp_path):
     """Config 2's shape (64 x 2^20, N = 1024, switch at block 512) on the real
-    parts of its samples, sampled blocks of every channel against the oracle."""
+    parts of its samples, in the launch configuration the benchmark times:
+    sampled blocks of every seventh channel against the oracle."""
     w = wl.config2()
     xs = harness.upload_inputs(w, "r32")
     ys = harness.alloc_outputs(w, "r32")
-    plan = vbw.Plan.from_workload(w, dtype="r32")
-    run_plan(plan, xs, ys)
+    plan = timed_shape_plan(w, tmp_path, dtype="r32")
+    run_timed_shape(plan, xs, ys, "real config2")
     rng = np.random.default_rng(8)
     worst = -np.inf
     for ci in range(0, len(w.channels), 7):
